@@ -1,0 +1,155 @@
+"""Throughput of the T3S3-DUGKS sweep on one MI355X.
+
+Workload: Taylor-Green vortex on a periodic 2048 x 2048 grid with the D2Q37
+velocity set, FP32 storage of the deviation f - w_q rho0 (the 2048^2 / D2Q37 /
+FP32-delta member of the Taylor-Green family at 256^2..2048^2, D2Q9 and D2Q37,
+FP64 vs FP32-delta).  The same grid in FP64 is timed beside it.  One "step"
+is one full T3S3 step (stage A + stage C) over every (cell, velocity) pair.
+
+Prints one JSON line.  Metric: G cell-velocity updates per second (cells * Q *
+steps / s / 1e9) plus the HBM-roofline fraction of the dominant kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--n", type=int, default=2048, help="cells per side")
+    ap.add_argument("--lattice", default="d2q37", choices=["d2q9", "d2q37"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tile", default="", help="tile as TXxTY")
+    return ap.parse_args()
+
+
+def make_case(n, lattice):
+    from paper_1709_05458_amd import cases as C
+    vs = C.d2q37(1.0 / 3.0) if lattice == "d2q37" else C.d2q9(1.0 / 3.0)
+    return C.tgv_case(n, vs, steps=1000)
+
+
+def time_run(case, precision, steps, warmup, tile):
+    import torch
+    from paper_1709_05458_amd import dugks
+    s = dugks.Solver(case, precision, tile=tile)
+    s.init_equilibrium(case.rho, case.ux, case.uy)
+    s.step(warmup)
+    s.sync()
+    torch.cuda.synchronize()
+    s.prof_begin(2 * steps + 8)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    a_ms, a_n = s.prof_query(dugks.K_STAGE_A)
+    c_ms, c_n = s.prof_query(dugks.K_STAGE_C)
+    s.prof_end()
+    s.sync()   # raises on a non-finite state
+    r, ux, uy = s.moments()
+    desc = s.describe()
+    s.close()
+    return {"ms_per_step": ms_total / steps, "stage_a_ms": a_ms, "stage_c_ms": c_ms,
+            "launches": (a_n, c_n), "variant": desc, "u_max": float(max(np.abs(ux).max(), np.abs(uy).max())),
+            "mass": float(r.mean())}
+
+
+def cpu_baseline(lattice):
+    """The oracle as it stands on the host cores, on a bounded sample of the
+    same workload (Taylor-Green, same velocity set, 256 x 256, a few steps)."""
+    import oracle
+    n = 256
+    case = make_case(n, lattice)
+    o = oracle.Oracle(case)
+    fh = o.init_fhat()
+    t0 = time.perf_counter()
+    o.run(fh, 1)
+    t1 = time.perf_counter() - t0
+    steps = max(2, min(200, int(math.ceil(15.0 / max(t1, 1e-3)))))   # about 15 s of CPU work
+    t0 = time.perf_counter()
+    o.run(fh, steps)
+    dt = time.perf_counter() - t0
+    pairs = n * n * case.vs.nq
+    return {"value": pairs * steps / dt / 1e9, "unit": "G cell-velocity updates/s",
+            "cores": o.num_threads(), "kind": "oracle",
+            "sample": f"Taylor-Green {n}x{n} {case.vs.name} FP64, {steps} steps ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_1709_05458_amd import dugks
+    torch.cuda.set_device(0)
+    tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
+    case = make_case(args.n, args.lattice)
+    Q = case.vs.nq
+    pairs = args.n * args.n * Q
+    print(f"# bench: TGV {args.n}^2 {case.vs.name} FP32-delta, {args.steps} steps", file=sys.stderr, flush=True)
+    r32 = time_run(case, dugks.FP32_DELTA, args.steps, args.warmup, tile)
+    print(f"# fp32-delta: {r32}", file=sys.stderr, flush=True)
+    r64 = None
+    if not args.no_fp64:
+        r64 = time_run(case, dugks.FP64, max(10, args.steps // 4), args.warmup, tile)
+        print(f"# fp64: {r64}", file=sys.stderr, flush=True)
+    gcups = pairs / (r32["ms_per_step"] * 1e-3) / 1e9
+    # dominant kernel: stage C reads tilde f (with halo, cached) and fhat and
+    # writes fhat(t_{n+1}): 3 stored elements per pair algorithmically
+    s = 4
+    bytes_c = 3 * s * pairs
+    achieved = bytes_c / (r32["stage_c_ms"] * 1e-3) / 1e9
+    out = {
+        "metric": "G cell-velocity updates/s per DUGKS step (FP32-delta; FP64 beside it) + %HBM peak",
+        "value": round(gcups, 3),
+        "unit": "G cell-velocity updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"taylor-green {args.n}x{args.n} periodic, {case.vs.name}, FP32-delta storage, T3S3",
+                   "cells": args.n * args.n, "velocities": Q, "pairs": pairs,
+                   "variant": r32["variant"]},
+        "roofline": {"bound": "hbm", "kernel": "stage C (sweep_small, STAGE=1)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": bytes_c, "launch_ms": round(r32["stage_c_ms"], 5),
+                     "stage_a_ms": round(r32["stage_a_ms"], 5)},
+    }
+    if r64:
+        g64 = pairs / (r64["ms_per_step"] * 1e-3) / 1e9
+        a64 = 3 * 8 * pairs / (r64["stage_c_ms"] * 1e-3) / 1e9
+        out["fp64"] = {"value": round(g64, 3), "ms_per_step": round(r64["ms_per_step"], 5),
+                       "stage_c_GBs": round(a64, 1), "frac": round(a64 / HBM_PEAK_GBS, 4),
+                       "stage_a_ms": round(r64["stage_a_ms"], 5), "stage_c_ms": round(r64["stage_c_ms"], 5)}
+    out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(args.lattice)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * dugks.h -- C ABI of the MI355X (gfx950) implementation of the per-step sweep
+ * of the third-order discrete unified gas kinetic scheme (T3S3-DUGKS) of
+ * Wu, Shu, Shi & Chen, arXiv 1709.05458 ("A third-order discrete unified gas
+ * kinetic scheme for continuum and rarefied flows: low-speed isothermal case").
+ *
+ * One time step (paper section "Computational sequence of the third-order
+ * DUGKS", steps (1)-(4), evolution equation feqIntD3rdHat2_DS) is two sweeps
+ * over every (cell, discrete velocity) pair:
+ *   stage A  steps (1)-(2): fhat(t_n) -> fbar^{+,dt/6} (eq. f_bar_1_6) ->
+ *            interface values at t_n + dt/6 (eqs. interfaceEvof, flux_DS) ->
+ *            interface moments, equilibrium and recovery (eq. recover2f) ->
+ *            micro-flux L* (eq. microflux) -> tilde f(t_n + dt/3)
+ *            (eq. f_tilde_1_3 and the T2 update of Remark I with step dt/3);
+ *   stage C  steps (3)-(4): tilde f(t') -> fbar^{+,5dt/12} (eq. fbp_5_12) ->
+ *            interface values, moments, recovery at t_n + 3dt/4 -> L** ->
+ *            fhat(t_{n+1}) = fhat^+ + 3/4 dt Omega(t') + dt/7 (3 L* + 4 L**).
+ *
+ * Conventions for every entry point:
+ *  - Every function returns 0 (DUGKS_OK) or a negative dugks_status code; no
+ *    C++ exception crosses this interface.  dugks_strerror() names a code and
+ *    dugks_last_error_message() gives the detail of the last failure on the
+ *    calling thread.
+ *  - Distribution arrays are double, layout [q][cell] with cell = j*nx + i
+ *    (x fastest); cell fields are double [cell].  `mem` says whether a pointer
+ *    is host (DUGKS_MEM_HOST) or device (DUGKS_MEM_DEVICE) memory.  The caller
+ *    owns every buffer it passes; the library copies what it keeps.
+ *  - All device work is queued on the stream given at creation.  Functions
+ *    that read results into host memory synchronise that stream.
+ *  - A handle must not be used from two threads at once.
+ */
+#ifndef DUGKS_H
+#define DUGKS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dugks dugks_t;
+
+enum dugks_status {
+    DUGKS_OK = 0,
+    DUGKS_EINVAL = -1,      /* invalid argument or descriptor */
+    DUGKS_EUNSTABLE = -2,   /* dt/tau above 12 somewhere (paper: von Neumann bound of P_n at a = 1/3) */
+    DUGKS_EMOMENT = -3,     /* weights miss sum w = 1 or sum w xi xi = RT I by more than 1e-10 */
+    DUGKS_ENOMEM = -4,      /* device or host allocation failed */
+    DUGKS_EDEVICE = -5,     /* a HIP runtime call failed */
+    DUGKS_ENONFINITE = -6,  /* a non-finite density appeared in the state */
+    DUGKS_ENOTSUP = -7      /* valid but not supported by this build */
+};
+
+enum dugks_bc {
+    DUGKS_BC_PERIODIC = 0,
+    DUGKS_BC_BOUNCE_BACK = 1,   /* paper eq. BB */
+    DUGKS_BC_DIFFUSE = 2        /* paper's diffuse-scattering rule */
+};
+
+enum dugks_side { DUGKS_WEST = 0, DUGKS_EAST = 1, DUGKS_SOUTH = 2, DUGKS_NORTH = 3 };
+
+enum dugks_precision {
+    DUGKS_FP64 = 0,        /* state stored and swept in double */
+    DUGKS_FP32_DELTA = 1   /* state stored as float g_q = f_q / w_q - rho0; moments in double */
+};
+
+enum dugks_mem { DUGKS_MEM_HOST = 0, DUGKS_MEM_DEVICE = 1 };
+
+enum dugks_flags {
+    DUGKS_ALLOW_MOMENT_DEFECT = 1   /* accept weights that are not moment-exact (e.g. Newton-Cotes) */
+};
+
+/* Creation descriptor.  Pointers are host pointers, read only during
+ * dugks_create. */
+typedef struct {
+    int nx, ny;             /* number of cells, each >= 3 */
+    const double *xf;       /* nx+1 strictly increasing face x-coordinates */
+    const double *yf;       /* ny+1 strictly increasing face y-coordinates */
+    int nq;                 /* number of discrete velocities, >= 1 */
+    const double *xi;       /* [2][nq]: xi[q] = x-component, xi[nq+q] = y-component */
+    const double *w;        /* [nq] equilibrium weights, Gaussian factor included:
+                             * f^eq_q = w_q rho [1 + xi.u/RT + (xi.u)^2/(2RT^2) - u^2/(2RT)]
+                             * (paper, low-Mach expansion of the Maxwellian) */
+    double RT;              /* gas constant times temperature, > 0 */
+    double dt;              /* time step, > 0 */
+    const double *tau;      /* [ny][nx] per-cell relaxation time, or NULL for tau0 */
+    double tau0;            /* uniform relaxation time when tau == NULL */
+    int bc[4];              /* dugks_bc per side (west, east, south, north);
+                             * periodic must be paired (west with east, south with north) */
+    double u_wall[4][2];    /* wall velocity per side */
+    int precision;          /* dugks_precision */
+    double rho0;            /* reference density of DUGKS_FP32_DELTA storage */
+    double taylor_quad;     /* coefficient of the quadratic term of the interface
+                             * expansion (eq. flux_DS): 1.0 as printed, 0.5 for the
+                             * Taylor polynomial; 0 selects 1.0 */
+    void *stream;           /* hipStream_t for all work, NULL = null stream */
+    int flags;              /* dugks_flags */
+    int tile_x, tile_y;     /* sweep tile in cells; 0 = library choice */
+} dugks_desc;
+
+/* Build a solver for one grid / velocity set / relaxation field (paper:
+ * finite-volume grid, discrete velocity sets, BGK relaxation time, walls).
+ * Checks: nx, ny >= 3; faces increasing; periodic sides paired; dt > 0,
+ * RT > 0, tau > 0; max dt/tau <= 12 (else DUGKS_EUNSTABLE); bounce-back needs
+ * every velocity to have a mirror with the same weight (else EINVAL); weight
+ * moments (else DUGKS_EMOMENT unless DUGKS_ALLOW_MOMENT_DEFECT).  On success
+ * *out owns device buffers sized 3 * nq * nx * ny elements plus small tables;
+ * the state is undefined until set_state or init_equilibrium. */
+int dugks_create(const dugks_desc *d, dugks_t **out);
+
+/* Release every resource of h.  h == NULL is a no-op. */
+int dugks_destroy(dugks_t *h);
+
+/* State at t_n from the physical distribution f [q][cell]; the library stores
+ * fhat = f - (dt/4) Omega(f) (paper eq. feqIntD3rdHat2 definitions). */
+int dugks_set_state(dugks_t *h, const double *f, int mem);
+
+/* f = E(rho, u) at every cell (paper: initial state is the equilibrium). */
+int dugks_init_equilibrium(dugks_t *h, const double *rho, const double *ux,
+                           const double *uy, int mem);
+
+/* Advance nsteps T3S3 steps (asynchronous on the stream). */
+int dugks_step(dugks_t *h, int nsteps);
+
+/* Cell density and velocity [cell] of the current state (moments of fhat,
+ * which equal those of f for moment-exact weights). */
+int dugks_moments(dugks_t *h, double *rho, double *ux, double *uy, int mem);
+
+/* Physical distribution f = (4 tau fhat + dt E) / (4 tau + dt), [q][cell]. */
+int dugks_get_state(dugks_t *h, double *f, int mem);
+
+/* The stored variable fhat itself, [q][cell], in double. */
+int dugks_get_fhat(dugks_t *h, double *fhat, int mem);
+
+/* Replace the relaxation-time field ([cell], > 0, dt/tau <= 12). */
+int dugks_set_tau(dugks_t *h, const double *tau, int mem);
+
+/* Block until all queued work of h is done; reports DUGKS_ENONFINITE if the
+ * density of the current state is not finite anywhere. */
+int dugks_sync(dugks_t *h);
+
+/* Gradient of loss = sum_j dL_drho_j rho_j(T) + dL_du_j . u_j(T) after
+ * nsteps steps from the physical initial state f0, with respect to f0
+ * ([q][cell]) and the per-cell tau field ([cell]).  The forward pass is
+ * recomputed from f0 with a checkpoint every ckpt_every steps.  Periodic,
+ * uniform grids only (else DUGKS_ENOTSUP).  dL_drho may be NULL (zero);
+ * dL_du is [2][cell]; outputs are caller-owned; dL_dtau may be NULL. */
+int dugks_backward(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
+                   const double *dL_drho, const double *dL_du,
+                   double *dL_df0, double *dL_dtau, int mem);
+
+/* Kernel timing by HIP events recorded around each launch on the stream.
+ * prof_begin clears the record (room for max_launches launches); after the
+ * stream is synchronised, prof_query returns the mean duration in ms and the
+ * count of launches of one kernel class (dugks_kernel). */
+enum dugks_kernel { DUGKS_K_STAGE_A = 0, DUGKS_K_STAGE_C = 1, DUGKS_K_AUX = 2, DUGKS_K_COUNT = 3 };
+int dugks_prof_begin(dugks_t *h, int max_launches);
+int dugks_prof_query(dugks_t *h, int kernel, double *mean_ms, int *count);
+int dugks_prof_end(dugks_t *h);
+
+/* Description of the chosen sweep: kernel variant name and tile. */
+int dugks_describe(dugks_t *h, char *buf, int len);
+
+const char *dugks_strerror(int code);
+const char *dugks_last_error_message(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DUGKS_H */

@@ -1,0 +1,710 @@
+// C ABI of the T3S3-DUGKS library (declarations and contracts in
+// include/dugks.h): descriptor validation, device buffers, per-stage tables
+// and launch sequencing.  Compiled by hipcc as host code.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dugks.h"
+#include "dugks_internal.h"
+
+using namespace dk;
+
+struct dugks {
+    SweepParams p{};
+    int lat = 0;          // 9, 37 (compile-time lattices) or 0 (generic)
+    bool delta = false;
+    hipStream_t stream = nullptr;
+    size_t elem = 8;      // bytes per stored element
+    void *state[2] = {nullptr, nullptr};
+    int cur = 0;
+    void *G = nullptr;    // stage A output
+    void *coefA = nullptr, *coefC = nullptr;
+    double h1 = 0, h2 = 0;
+    int *d_bad = nullptr;
+    std::vector<void *> allocs;
+    // timing
+    std::vector<hipEvent_t> ev;   // pairs
+    std::vector<int> ev_kind;
+    int prof_max = 0, prof_n = 0;
+    bool prof_on = false;
+    std::string variant;
+};
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHECK(expr)                                                                     \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(DUGKS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static int dalloc(dugks *h, void **p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+    if (e != hipSuccess) return fail(DUGKS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    h->allocs.push_back(*p);
+    return DUGKS_OK;
+}
+
+template <class T>
+static int upload(dugks *h, const T *src, size_t count, const T **dst)
+{
+    void *p = nullptr;
+    int rc = dalloc(h, &p, sizeof(T) * count);
+    if (rc) return rc;
+    HIPCHECK(hipMemcpy(p, src, sizeof(T) * count, hipMemcpyHostToDevice));
+    *dst = (const T *)p;
+    return DUGKS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Lattice detection: xi_q == c * e_q for the compiled integer lattices.
+// ---------------------------------------------------------------------------
+static const int kD2Q9x[9] = {-1, -1, -1, 0, 0, 0, 1, 1, 1};
+static const int kD2Q9y[9] = {-1, 0, 1, -1, 0, 1, -1, 0, 1};
+static const int kD2Q37x[37] = {0, -1, 0, 0, 1, -1, -1, 1, 1, -2, 0, 0, 2, -2, -2, -1, -1, 1, 1,
+                                2, 2, -2, -2, 2, 2, -3, 0, 0, 3, -3, -3, -1, -1, 1, 1, 3, 3};
+static const int kD2Q37y[37] = {0, 0, -1, 1, 0, -1, 1, -1, 1, 0, -2, 2, 0, -1, 1, -2, 2, -2, 2,
+                                -1, 1, -2, 2, -2, 2, 0, -3, 3, 0, -1, 1, -3, 3, -3, 3, -1, 1};
+
+static bool match_lattice(const double *xi, int nq, const int *ex, const int *ey, int Q, double &c)
+{
+    if (nq != Q) return false;
+    double m = 0;
+    int em = 0;
+    for (int q = 0; q < Q; q++) {
+        m = std::fmax(m, std::fabs(xi[q]));
+        em = std::max(em, std::abs(ex[q]));
+    }
+    if (m <= 0 || em == 0) return false;
+    c = m / em;
+    for (int q = 0; q < Q; q++) {
+        if (std::fabs(xi[q] - c * ex[q]) > 1e-12 * m) return false;
+        if (std::fabs(xi[nq + q] - c * ey[q]) > 1e-12 * m) return false;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// Fast-path coefficients: one linear combination per (q, face orientation)
+// for uniform spacing (central 3-point derivatives, upwind choice by the sign
+// of the normal velocity, mean of both sides when it is zero).
+// ---------------------------------------------------------------------------
+static void expansion3x3(double dn, double dt_, double hn, double ht, double kappa, double C[3][3])
+{
+    // C[a][b]: a = offset along the face normal (-1..1), b = tangential offset
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) {
+            const int oa = a - 1, ob = b - 1;
+            const double e_a = oa == 0, e_b = ob == 0;
+            const double d1a = oa / (2.0 * hn), d2a = (oa == 0 ? -2.0 : 1.0) / (hn * hn);
+            const double d1b = ob / (2.0 * ht), d2b = (ob == 0 ? -2.0 : 1.0) / (ht * ht);
+            C[a][b] = e_a * e_b + dn * d1a * e_b + dt_ * e_a * d1b +
+                      kappa * (dn * dn * d2a * e_b + 2.0 * dn * dt_ * d1a * d1b + dt_ * dt_ * e_a * d2b);
+        }
+}
+
+static std::vector<double> fast_coefs(const double *xi, int nq, double dx, double dy, double h,
+                                      double kappa)
+{
+    std::vector<double> c((size_t)nq * 24, 0.0);
+    for (int q = 0; q < nq; q++) {
+        const double ex = xi[q], ey = xi[nq + q];
+        // x-faces: window columns k = 0..3 <-> offsets -2..1 from the right cell
+        for (int side = 0; side < 2; side++) {   // 0: upwind left, 1: upwind right
+            double wgt;
+            if (ex > 0) wgt = side == 0 ? 1.0 : 0.0;
+            else if (ex < 0) wgt = side == 1 ? 1.0 : 0.0;
+            else wgt = 0.5;
+            if (wgt == 0.0) continue;
+            const double dn = (side == 0 ? 0.5 * dx : -0.5 * dx) - ex * h;
+            const double dtn = -ey * h;
+            double C[3][3];
+            expansion3x3(dn, dtn, dx, dy, kappa, C);
+            const int uoff = side == 0 ? -1 : 0;
+            for (int a = 0; a < 3; a++)
+                for (int b = 0; b < 3; b++) {
+                    const int k = uoff + (a - 1) + 2;
+                    c[(size_t)q * 24 + k * 3 + b] += wgt * C[a][b];
+                }
+        }
+        // y-faces: window rows k = 0..3 <-> offsets -2..1 from the upper cell
+        for (int side = 0; side < 2; side++) {
+            double wgt;
+            if (ey > 0) wgt = side == 0 ? 1.0 : 0.0;
+            else if (ey < 0) wgt = side == 1 ? 1.0 : 0.0;
+            else wgt = 0.5;
+            if (wgt == 0.0) continue;
+            const double dn = (side == 0 ? 0.5 * dy : -0.5 * dy) - ey * h;
+            const double dtn = -ex * h;
+            double C[3][3];
+            expansion3x3(dn, dtn, dy, dx, kappa, C);
+            const int uoff = side == 0 ? -1 : 0;
+            for (int a = 0; a < 3; a++)
+                for (int b = 0; b < 3; b++) {
+                    const int k = uoff + (a - 1) + 2;
+                    c[(size_t)q * 24 + 12 + k * 3 + b] += wgt * C[a][b];
+                }
+        }
+    }
+    return c;
+}
+
+// ---------------------------------------------------------------------------
+// Geometry tables (general path)
+// ---------------------------------------------------------------------------
+static double centre(const double *f, int n, int i)
+{
+    const double L = f[n] - f[0];
+    double s = 0;
+    while (i < 0) { i += n; s -= L; }
+    while (i >= n) { i -= n; s += L; }
+    return 0.5 * (f[i] + f[i + 1]) + s;
+}
+
+static void axis_tables(const double *f, int n, bool periodic, std::vector<double> &dl,
+                        std::vector<double> &dr, std::vector<int> &off, std::vector<double> &d1,
+                        std::vector<double> &d2, std::vector<double> &inv)
+{
+    dl.assign(n + 1, 0.0);
+    dr.assign(n + 1, 0.0);
+    off.assign(n, -1);
+    d1.assign(3 * n, 0.0);
+    d2.assign(3 * n, 0.0);
+    inv.assign(n, 0.0);
+    for (int k = 0; k <= n; k++) {
+        dl[k] = f[k] - centre(f, n, k - 1);
+        dr[k] = f[k] - centre(f, n, k);
+    }
+    for (int i = 0; i < n; i++) {
+        int o0 = -1;
+        if (!periodic) {
+            if (i == 0) o0 = 0;
+            else if (i == n - 1) o0 = -2;
+        }
+        off[i] = o0;
+        const double xc = centre(f, n, i);
+        double pp[3];
+        for (int k = 0; k < 3; k++) pp[k] = centre(f, n, i + o0 + k) - xc;
+        for (int k = 0; k < 3; k++) {
+            const int a = (k + 1) % 3, b = (k + 2) % 3;
+            const double den = (pp[k] - pp[a]) * (pp[k] - pp[b]);
+            d1[3 * i + k] = -(pp[a] + pp[b]) / den;
+            d2[3 * i + k] = 2.0 / den;
+        }
+        inv[i] = 1.0 / (f[i + 1] - f[i]);
+    }
+}
+
+static bool is_uniform(const double *f, int n)
+{
+    const double d0 = f[1] - f[0];
+    for (int i = 0; i < n; i++)
+        if (std::fabs((f[i + 1] - f[i]) - d0) > 1e-12 * std::fabs(d0)) return false;
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// API
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *dugks_strerror(int code)
+{
+    switch (code) {
+    case DUGKS_OK: return "ok";
+    case DUGKS_EINVAL: return "invalid argument";
+    case DUGKS_EUNSTABLE: return "dt/tau above the stability bound 12";
+    case DUGKS_EMOMENT: return "weights are not moment-exact";
+    case DUGKS_ENOMEM: return "out of memory";
+    case DUGKS_EDEVICE: return "HIP runtime error";
+    case DUGKS_ENONFINITE: return "non-finite state";
+    case DUGKS_ENOTSUP: return "not supported";
+    default: return "unknown error";
+    }
+}
+
+const char *dugks_last_error_message(void) { return g_err.c_str(); }
+
+int dugks_destroy(dugks_t *h)
+{
+    if (!h) return DUGKS_OK;
+    for (auto &e : h->ev) (void)hipEventDestroy(e);
+    for (void *p : h->allocs) (void)hipFree(p);
+    delete h;
+    return DUGKS_OK;
+}
+
+static int validate(const dugks_desc *d)
+{
+    if (!d) return fail(DUGKS_EINVAL, "null descriptor");
+    if (d->nx < 3 || d->ny < 3) return fail(DUGKS_EINVAL, "nx and ny must be >= 3");
+    if (!d->xf || !d->yf || !d->xi || !d->w) return fail(DUGKS_EINVAL, "null grid or velocity array");
+    if (d->nq < 1) return fail(DUGKS_EINVAL, "nq must be >= 1");
+    for (int i = 0; i < d->nx; i++)
+        if (!(d->xf[i + 1] > d->xf[i])) return fail(DUGKS_EINVAL, "xf not increasing");
+    for (int j = 0; j < d->ny; j++)
+        if (!(d->yf[j + 1] > d->yf[j])) return fail(DUGKS_EINVAL, "yf not increasing");
+    if (!(d->RT > 0) || !(d->dt > 0)) return fail(DUGKS_EINVAL, "RT and dt must be > 0");
+    for (int k = 0; k < 4; k++)
+        if (d->bc[k] < 0 || d->bc[k] > 2) return fail(DUGKS_EINVAL, "unknown boundary kind");
+    if ((d->bc[0] == DUGKS_BC_PERIODIC) != (d->bc[1] == DUGKS_BC_PERIODIC) ||
+        (d->bc[2] == DUGKS_BC_PERIODIC) != (d->bc[3] == DUGKS_BC_PERIODIC))
+        return fail(DUGKS_EINVAL, "periodic sides must be paired");
+    if (d->precision != DUGKS_FP64 && d->precision != DUGKS_FP32_DELTA)
+        return fail(DUGKS_EINVAL, "unknown precision");
+    // CFL: the characteristic foot point must stay within the upwind cell's stencil
+    double cmax = 0;
+    for (int q = 0; q < 2 * d->nq; q++) cmax = std::fmax(cmax, std::fabs(d->xi[q]));
+    double dmin = 1e300;
+    for (int i = 0; i < d->nx; i++) dmin = std::fmin(dmin, d->xf[i + 1] - d->xf[i]);
+    for (int j = 0; j < d->ny; j++) dmin = std::fmin(dmin, d->yf[j + 1] - d->yf[j]);
+    if (cmax * d->dt > dmin * (1.0 + 1e-12)) return fail(DUGKS_EINVAL, "CFL number above 1");
+    return DUGKS_OK;
+}
+
+static int check_tau(const double *tau, long long n, double tau0, double dt)
+{
+    if (tau) {
+        for (long long k = 0; k < n; k++) {
+            if (!(tau[k] > 0)) return fail(DUGKS_EINVAL, "tau must be > 0");
+            if (dt / tau[k] > 12.0 * (1 + 1e-12)) return fail(DUGKS_EUNSTABLE, "dt/tau > 12");
+        }
+    } else {
+        if (!(tau0 > 0)) return fail(DUGKS_EINVAL, "tau0 must be > 0");
+        if (dt / tau0 > 12.0 * (1 + 1e-12)) return fail(DUGKS_EUNSTABLE, "dt/tau > 12");
+    }
+    return DUGKS_OK;
+}
+
+int dugks_create(const dugks_desc *d, dugks_t **out)
+{
+    if (!out) return fail(DUGKS_EINVAL, "null output handle");
+    *out = nullptr;
+    int rc = validate(d);
+    if (rc) return rc;
+    const long long ncell = (long long)d->nx * d->ny;
+    if ((rc = check_tau(d->tau, ncell, d->tau0, d->dt))) return rc;
+    const int nq = d->nq;
+    const double *xi = d->xi, *eta = d->xi + nq;
+
+    // weight moments
+    double M0 = 0, M1x = 0, M1y = 0, Mxx = 0, Myy = 0, Mxy = 0;
+    for (int q = 0; q < nq; q++) {
+        M0 += d->w[q];
+        M1x += d->w[q] * xi[q];
+        M1y += d->w[q] * eta[q];
+        Mxx += d->w[q] * xi[q] * xi[q];
+        Myy += d->w[q] * eta[q] * eta[q];
+        Mxy += d->w[q] * xi[q] * eta[q];
+    }
+    const double defect = std::fmax(std::fmax(std::fabs(M0 - 1), std::fabs(Mxx / d->RT - 1)),
+                                    std::fmax(std::fabs(Myy / d->RT - 1), std::fabs(Mxy / d->RT)));
+    if (defect > 1e-10 && !(d->flags & DUGKS_ALLOW_MOMENT_DEFECT))
+        return fail(DUGKS_EMOMENT, "weight moment defect " + std::to_string(defect));
+
+    // walls need mirrors (bounce-back) / nonzero leaving flux (diffuse)
+    std::vector<int> opp(nq, -1);
+    double cm = 0;
+    for (int q = 0; q < nq; q++) cm = std::fmax(cm, std::fmax(std::fabs(xi[q]), std::fabs(eta[q])));
+    for (int q = 0; q < nq; q++)
+        for (int r = 0; r < nq; r++)
+            if (std::fabs(xi[q] + xi[r]) <= 1e-12 * cm && std::fabs(eta[q] + eta[r]) <= 1e-12 * cm) {
+                opp[q] = r;
+                break;
+            }
+    bool any_bb = false;
+    for (int k = 0; k < 4; k++) any_bb |= d->bc[k] == DUGKS_BC_BOUNCE_BACK;
+    if (any_bb)
+        for (int q = 0; q < nq; q++)
+            if (opp[q] < 0 || std::fabs(d->w[opp[q]] - d->w[q]) > 1e-14 * std::fabs(d->w[q]))
+                return fail(DUGKS_EINVAL, "bounce-back needs a mirror velocity with equal weight");
+
+    dugks *h = new dugks();
+    h->stream = (hipStream_t)d->stream;
+    h->delta = d->precision == DUGKS_FP32_DELTA;
+    h->elem = h->delta ? 4 : 8;
+    SweepParams &p = h->p;
+    p.nx = d->nx;
+    p.ny = d->ny;
+    p.ncell = ncell;
+    p.perx = d->bc[0] == DUGKS_BC_PERIODIC;
+    p.pery = d->bc[2] == DUGKS_BC_PERIODIC;
+    p.nq = nq;
+    p.RT = d->RT;
+    p.dt = d->dt;
+    p.rho0 = h->delta ? d->rho0 : 0.0;
+    if (h->delta && !(d->rho0 > 0)) {
+        delete h;
+        return fail(DUGKS_EINVAL, "FP32-delta storage needs rho0 > 0");
+    }
+    p.M0m1 = M0 - 1.0;
+    p.M1x = M1x;
+    p.M1y = M1y;
+    p.kappa = d->taylor_quad > 0 ? d->taylor_quad : 1.0;
+    p.tau0 = d->tau0;
+    p.tau_field = d->tau != nullptr;
+    p.literal_fbp = 0;
+    for (int k = 0; k < 4; k++) {
+        p.bc[k] = d->bc[k];
+        p.uw[k][0] = d->u_wall[k][0];
+        p.uw[k][1] = d->u_wall[k][1];
+    }
+
+    // lattice
+    double c = 0;
+    if (match_lattice(d->xi, nq, kD2Q9x, kD2Q9y, 9, c)) h->lat = 9;
+    else if (match_lattice(d->xi, nq, kD2Q37x, kD2Q37y, 37, c)) h->lat = 37;
+    else {
+        delete h;
+        return fail(DUGKS_ENOTSUP, "velocity set is not D2Q9 or D2Q37 in the library's order");
+    }
+    p.clat = c;
+
+    // tile
+    const int lx = d->tile_x > 0 ? d->tile_x : 32;
+    const int ly = d->tile_y > 0 ? d->tile_y : (h->lat == 37 && !h->delta ? 4 : 8);
+    if (lx * ly > 512 || lx * ly < 64 || lx < 2 || ly < 2) {
+        delete h;
+        return fail(DUGKS_EINVAL, "tile must hold 64..512 cells");
+    }
+    p.tile_x = lx;
+    p.tile_y = ly;
+    const size_t smem = h->elem * nq * (size_t)(lx + 4) * (ly + 4);
+    if (smem > 160 * 1024) {
+        delete h;
+        return fail(DUGKS_EINVAL, "tile too large for LDS");
+    }
+    {
+        hipError_t e = set_stage_smem(h->lat, h->delta, smem);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(DUGKS_EDEVICE, std::string("LDS size: ") + hipGetErrorString(e));
+        }
+    }
+
+    // grid
+    const bool unif = is_uniform(d->xf, d->nx) && is_uniform(d->yf, d->ny);
+    p.uniform = unif;
+    p.inv_dx = 1.0 / (d->xf[1] - d->xf[0]);
+    p.inv_dy = 1.0 / (d->yf[1] - d->yf[0]);
+    std::vector<double> dxl, dxr, sxd1, sxd2, ixd, dyl, dyr, syd1, syd2, iyd;
+    std::vector<int> sxo, syo;
+    axis_tables(d->xf, d->nx, p.perx, dxl, dxr, sxo, sxd1, sxd2, ixd);
+    axis_tables(d->yf, d->ny, p.pery, dyl, dyr, syo, syd1, syd2, iyd);
+#define UP(vec, dst)                                                        \
+    if ((rc = upload(h, vec.data(), vec.size(), &dst))) { dugks_destroy(h); return rc; }
+    UP(dxl, p.g.dxl) UP(dxr, p.g.dxr) UP(dyl, p.g.dyl) UP(dyr, p.g.dyr)
+    UP(sxo, p.g.sx_off) UP(syo, p.g.sy_off)
+    UP(sxd1, p.g.sx_d1) UP(sxd2, p.g.sx_d2) UP(syd1, p.g.sy_d1) UP(syd2, p.g.sy_d2)
+    UP(ixd, p.g.inv_dx) UP(iyd, p.g.inv_dy)
+    std::vector<double> vxi(xi, xi + nq), veta(eta, eta + nq), vw(d->w, d->w + nq);
+    UP(vxi, p.xi) UP(veta, p.eta) UP(vw, p.w) UP(opp, p.opp)
+    if (d->tau) {
+        std::vector<double> vt(d->tau, d->tau + ncell);
+        UP(vt, p.tau)
+    }
+
+    // diffuse-wall tables
+    std::vector<double> wallE(4 * (size_t)nq, 0.0);
+    for (int k = 0; k < 4; k++) {
+        const double nxw = k == 0 ? -1.0 : k == 1 ? 1.0 : 0.0;
+        const double nyw = k == 2 ? -1.0 : k == 3 ? 1.0 : 0.0;
+        const double ux = d->u_wall[k][0], uy = d->u_wall[k][1];
+        double den = 0, off = 0, m0 = 0, mx = 0, my = 0, w0 = 0, wx = 0, wy = 0;
+        for (int q = 0; q < nq; q++) {
+            const double eu = xi[q] * ux + eta[q] * uy, uu = ux * ux + uy * uy;
+            const double P = 1.0 + eu / d->RT + eu * eu / (2 * d->RT * d->RT) - uu / (2 * d->RT);
+            wallE[(size_t)k * nq + q] = h->delta ? P : d->w[q] * P;
+            const double xn = xi[q] * nxw + eta[q] * nyw;
+            if (xn < 0) {
+                den += -xn * d->w[q] * P;
+                m0 += d->w[q] * P;
+                mx += xi[q] * d->w[q] * P;
+                my += eta[q] * d->w[q] * P;
+                w0 += d->w[q];
+                wx += xi[q] * d->w[q];
+                wy += eta[q] * d->w[q];
+            } else if (xn > 0) {
+                off += xn * d->w[q];
+            }
+        }
+        p.ds_den[k] = den;
+        p.ds_num_off[k] = h->delta ? d->rho0 * off : 0.0;
+        p.ds_m[k][0] = m0; p.ds_m[k][1] = mx; p.ds_m[k][2] = my;
+        p.ds_w[k][0] = w0; p.ds_w[k][1] = wx; p.ds_w[k][2] = wy;
+        if (d->bc[k] == DUGKS_BC_DIFFUSE && !(den > 0)) {
+            dugks_destroy(h);
+            return fail(DUGKS_EINVAL, "diffuse wall with no leaving velocity");
+        }
+    }
+    UP(wallE, p.wall_E)
+
+    // fast-path coefficients of both stages
+    h->h1 = d->dt / 6.0;
+    h->h2 = 5.0 * d->dt / 12.0;
+    {
+        const double dx = d->xf[1] - d->xf[0], dy = d->yf[1] - d->yf[0];
+        std::vector<double> cA = fast_coefs(d->xi, nq, dx, dy, h->h1, p.kappa);
+        std::vector<double> cC = fast_coefs(d->xi, nq, dx, dy, h->h2, p.kappa);
+        if (h->delta) {
+            std::vector<float> fA(cA.begin(), cA.end()), fC(cC.begin(), cC.end());
+            const float *a, *b;
+            UP(fA, a) UP(fC, b)
+            h->coefA = (void *)a;
+            h->coefC = (void *)b;
+        } else {
+            const double *a, *b;
+            UP(cA, a) UP(cC, b)
+            h->coefA = (void *)a;
+            h->coefC = (void *)b;
+        }
+    }
+#undef UP
+
+    // state buffers
+    const size_t bytes = h->elem * (size_t)nq * ncell;
+    if ((rc = dalloc(h, &h->state[0], bytes)) || (rc = dalloc(h, &h->state[1], bytes)) ||
+        (rc = dalloc(h, &h->G, bytes))) {
+        dugks_destroy(h);
+        return rc;
+    }
+    void *bad = nullptr;
+    if ((rc = dalloc(h, &bad, sizeof(int)))) { dugks_destroy(h); return rc; }
+    h->d_bad = (int *)bad;
+    HIPCHECK(hipMemset(h->d_bad, 0, sizeof(int)));
+    char buf[128];
+    snprintf(buf, sizeof buf, "small-Q D2Q%d %s tile %dx%d %s", h->lat, h->delta ? "fp32-delta" : "fp64",
+             lx, ly, unif ? "uniform" : "non-uniform");
+    h->variant = buf;
+    *out = h;
+    return DUGKS_OK;
+}
+
+int dugks_describe(dugks_t *h, char *buf, int len)
+{
+    if (!h || !buf || len <= 0) return fail(DUGKS_EINVAL, "bad arguments");
+    snprintf(buf, len, "%s", h->variant.c_str());
+    return DUGKS_OK;
+}
+
+// staging helper: device copy of a host array (or the device pointer itself)
+struct Staged {
+    double *dev = nullptr;
+    bool owned = false;
+    ~Staged() { if (owned) (void)hipFree(dev); }
+};
+
+static int stage_in(const double *src, size_t count, int mem, Staged &s, hipStream_t st)
+{
+    if (mem == DUGKS_MEM_DEVICE) {
+        s.dev = const_cast<double *>(src);
+        return DUGKS_OK;
+    }
+    if (mem != DUGKS_MEM_HOST) return fail(DUGKS_EINVAL, "mem must be host or device");
+    hipError_t e = hipMalloc((void **)&s.dev, sizeof(double) * (count ? count : 1));
+    if (e != hipSuccess) return fail(DUGKS_ENOMEM, "staging buffer");
+    s.owned = true;
+    HIPCHECK(hipMemcpyAsync(s.dev, src, sizeof(double) * count, hipMemcpyHostToDevice, st));
+    return DUGKS_OK;
+}
+
+int dugks_set_state(dugks_t *h, const double *f, int mem)
+{
+    if (!h || !f) return fail(DUGKS_EINVAL, "null argument");
+    Staged s;
+    int rc = stage_in(f, (size_t)h->p.nq * h->p.ncell, mem, s, h->stream);
+    if (rc) return rc;
+    HIPCHECK(launch_set_state(h->p, h->delta, s.dev, h->state[h->cur], h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return DUGKS_OK;
+}
+
+int dugks_init_equilibrium(dugks_t *h, const double *rho, const double *ux, const double *uy,
+                           int mem)
+{
+    if (!h || !rho || !ux || !uy) return fail(DUGKS_EINVAL, "null argument");
+    Staged a, b, c;
+    const size_t n = h->p.ncell;
+    int rc;
+    if ((rc = stage_in(rho, n, mem, a, h->stream)) || (rc = stage_in(ux, n, mem, b, h->stream)) ||
+        (rc = stage_in(uy, n, mem, c, h->stream)))
+        return rc;
+    HIPCHECK(launch_init_eq(h->p, h->delta, a.dev, b.dev, c.dev, h->state[h->cur], h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return DUGKS_OK;
+}
+
+static int record(dugks *h, int kind, bool start)
+{
+    if (!h->prof_on || h->prof_n >= h->prof_max) return DUGKS_OK;
+    const int k = h->prof_n;
+    HIPCHECK(hipEventRecord(h->ev[2 * k + (start ? 0 : 1)], h->stream));
+    if (!start) {
+        h->ev_kind[k] = kind;
+        h->prof_n++;
+    }
+    return DUGKS_OK;
+}
+
+int dugks_step(dugks_t *h, int nsteps)
+{
+    if (!h || nsteps < 0) return fail(DUGKS_EINVAL, "bad arguments");
+    for (int s = 0; s < nsteps; s++) {
+        void *X = h->state[h->cur], *Y = h->state[1 - h->cur];
+        int rc;
+        if ((rc = record(h, KC_STAGE_A, true))) return rc;
+        HIPCHECK(launch_stage(0, h->lat, h->delta, h->p, h->h1, X, nullptr, h->G, h->coefA, h->stream));
+        if ((rc = record(h, KC_STAGE_A, false))) return rc;
+        if ((rc = record(h, KC_STAGE_C, true))) return rc;
+        HIPCHECK(launch_stage(1, h->lat, h->delta, h->p, h->h2, h->G, X, Y, h->coefC, h->stream));
+        if ((rc = record(h, KC_STAGE_C, false))) return rc;
+        h->cur = 1 - h->cur;
+    }
+    return DUGKS_OK;
+}
+
+static int stage_out(dugks *h, double *dst, size_t count, int mem, Staged &s)
+{
+    if (mem == DUGKS_MEM_DEVICE) {
+        s.dev = dst;
+        return DUGKS_OK;
+    }
+    if (mem != DUGKS_MEM_HOST) return fail(DUGKS_EINVAL, "mem must be host or device");
+    hipError_t e = hipMalloc((void **)&s.dev, sizeof(double) * (count ? count : 1));
+    if (e != hipSuccess) return fail(DUGKS_ENOMEM, "staging buffer");
+    s.owned = true;
+    return DUGKS_OK;
+}
+
+static int finish_out(dugks *h, double *dst, size_t count, int mem, Staged &s)
+{
+    if (mem == DUGKS_MEM_HOST) {
+        HIPCHECK(hipMemcpyAsync(dst, s.dev, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream));
+        HIPCHECK(hipStreamSynchronize(h->stream));
+    }
+    return DUGKS_OK;
+}
+
+int dugks_moments(dugks_t *h, double *rho, double *ux, double *uy, int mem)
+{
+    if (!h) return fail(DUGKS_EINVAL, "null handle");
+    const size_t n = h->p.ncell;
+    Staged a, b, c;
+    int rc;
+    if ((rho && (rc = stage_out(h, rho, n, mem, a))) || (ux && (rc = stage_out(h, ux, n, mem, b))) ||
+        (uy && (rc = stage_out(h, uy, n, mem, c))))
+        return rc;
+    HIPCHECK(launch_moments(h->p, h->delta, h->state[h->cur], a.dev, b.dev, c.dev, nullptr, h->stream));
+    if (rho && (rc = finish_out(h, rho, n, mem, a))) return rc;
+    if (ux && (rc = finish_out(h, ux, n, mem, b))) return rc;
+    if (uy && (rc = finish_out(h, uy, n, mem, c))) return rc;
+    return DUGKS_OK;
+}
+
+static int get_dist(dugks_t *h, double *f, int mem, int physical)
+{
+    if (!h || !f) return fail(DUGKS_EINVAL, "null argument");
+    const size_t n = (size_t)h->p.nq * h->p.ncell;
+    Staged s;
+    int rc = stage_out(h, f, n, mem, s);
+    if (rc) return rc;
+    HIPCHECK(launch_get_state(h->p, h->delta, h->state[h->cur], s.dev, physical, h->stream));
+    return finish_out(h, f, n, mem, s);
+}
+
+int dugks_get_state(dugks_t *h, double *f, int mem) { return get_dist(h, f, mem, 1); }
+int dugks_get_fhat(dugks_t *h, double *f, int mem) { return get_dist(h, f, mem, 0); }
+
+int dugks_set_tau(dugks_t *h, const double *tau, int mem)
+{
+    if (!h || !tau) return fail(DUGKS_EINVAL, "null argument");
+    if (!h->p.tau_field) return fail(DUGKS_EINVAL, "handle was created with a uniform tau");
+    const size_t n = h->p.ncell;
+    std::vector<double> host(n);
+    if (mem == DUGKS_MEM_DEVICE) {
+        HIPCHECK(hipMemcpy(host.data(), tau, sizeof(double) * n, hipMemcpyDeviceToHost));
+    } else {
+        memcpy(host.data(), tau, sizeof(double) * n);
+    }
+    int rc = check_tau(host.data(), (long long)n, 0, h->p.dt);
+    if (rc) return rc;
+    HIPCHECK(hipMemcpyAsync((void *)h->p.tau, host.data(), sizeof(double) * n, hipMemcpyHostToDevice,
+                            h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return DUGKS_OK;
+}
+
+int dugks_sync(dugks_t *h)
+{
+    if (!h) return fail(DUGKS_EINVAL, "null handle");
+    HIPCHECK(hipMemsetAsync(h->d_bad, 0, sizeof(int), h->stream));
+    HIPCHECK(launch_moments(h->p, h->delta, h->state[h->cur], nullptr, nullptr, nullptr, h->d_bad,
+                            h->stream));
+    int bad = 0;
+    HIPCHECK(hipMemcpyAsync(&bad, h->d_bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    if (bad) return fail(DUGKS_ENONFINITE, "non-finite density in the state");
+    return DUGKS_OK;
+}
+
+int dugks_prof_begin(dugks_t *h, int max_launches)
+{
+    if (!h || max_launches < 1) return fail(DUGKS_EINVAL, "bad arguments");
+    for (auto &e : h->ev) (void)hipEventDestroy(e);
+    h->ev.assign(2 * (size_t)max_launches, nullptr);
+    for (auto &e : h->ev) HIPCHECK(hipEventCreate(&e));
+    h->ev_kind.assign(max_launches, -1);
+    h->prof_max = max_launches;
+    h->prof_n = 0;
+    h->prof_on = true;
+    return DUGKS_OK;
+}
+
+int dugks_prof_query(dugks_t *h, int kernel, double *mean_ms, int *count)
+{
+    if (!h || !mean_ms || !count) return fail(DUGKS_EINVAL, "null argument");
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    double sum = 0;
+    int c = 0;
+    for (int k = 0; k < h->prof_n; k++) {
+        if (h->ev_kind[k] != kernel) continue;
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, h->ev[2 * k], h->ev[2 * k + 1]));
+        sum += ms;
+        c++;
+    }
+    *mean_ms = c ? sum / c : 0.0;
+    *count = c;
+    return DUGKS_OK;
+}
+
+int dugks_prof_end(dugks_t *h)
+{
+    if (!h) return fail(DUGKS_EINVAL, "null handle");
+    h->prof_on = false;
+    return DUGKS_OK;
+}
+
+int dugks_backward(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
+                   const double *dL_drho, const double *dL_du, double *dL_df0, double *dL_dtau,
+                   int mem)
+{
+    (void)h; (void)f0; (void)nsteps; (void)ckpt_every; (void)dL_drho; (void)dL_du;
+    (void)dL_df0; (void)dL_dtau; (void)mem;
+    return fail(DUGKS_ENOTSUP, "adjoint not built yet");
+}
+
+}  // extern "C"

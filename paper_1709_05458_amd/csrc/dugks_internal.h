@@ -1,0 +1,74 @@
+// Internal declarations shared by the C-ABI host code and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dk {
+
+// Geometry tables for the general (walls / non-uniform) reconstruction path.
+// All device pointers.  Periodic neighbours are expressed through the face
+// offsets dxl/dxr, which already include the periodic image shift.
+struct Geometry {
+    const double *dxl, *dxr;   // [nx+1]: xf[f] - xc(f-1), xf[f] - xc(f)
+    const double *dyl, *dyr;   // [ny+1]
+    const int *sx_off, *sy_off;         // [n]: first cell offset of the 3-point stencil (-1, 0, -2)
+    const double *sx_d1, *sx_d2;        // [nx][3] derivative weights at the cell centre
+    const double *sy_d1, *sy_d2;        // [ny][3]
+    const double *inv_dx, *inv_dy;      // [nx], [ny] 1 / cell width
+};
+
+// Everything a sweep kernel needs; passed by value as a kernel argument.
+struct SweepParams {
+    int nx, ny;
+    long long ncell;
+    int perx, pery;          // periodic in x / y
+    int uniform;             // uniform spacing in both directions
+    int nq;
+    double RT, dt;
+    double rho0;             // FP32-delta reference density (0 for FP64 storage)
+    double M0m1;             // sum w - 1
+    double M1x, M1y;         // sum w xi
+    double kappa;            // coefficient of the quadratic expansion term
+    double clat;             // lattice scale (compile-time lattices: xi = clat * e)
+    double inv_dx, inv_dy;   // uniform grids
+    // relaxation time
+    const double *tau;       // [cell] or nullptr
+    double tau0;
+    int tau_field;
+    int literal_fbp;
+    Geometry g;
+    // velocity set (device)
+    const double *xi, *eta, *w;
+    const int *opp;
+    // walls
+    int bc[4];
+    double uw[4][2];
+    const double *wall_E;    // [4][nq]: storage-scaled E_q(1, u_w) of each side
+    double ds_den[4];        // sum over leaving q of |xi.n| w_q P_q(u_w)
+    double ds_num_off[4];    // FP32-delta: rho0 * sum over arriving q of (xi.n) w_q
+    double ds_m[4][3];       // sum over leaving q of (1, xi, eta) w_q P_q(u_w)
+    double ds_w[4][3];       // sum over leaving q of (1, xi, eta) w_q
+    int tile_x, tile_y;
+};
+
+// Kernel classes for event timing.
+enum KernelClass { KC_STAGE_A = 0, KC_STAGE_C = 1, KC_AUX = 2, KC_COUNT = 3 };
+
+// Host launchers (defined in sweep.hip).  `lat`: 0 generic, 9 D2Q9, 37 D2Q37.
+// `delta`: FP32-delta storage (float) else FP64 storage (double).
+hipError_t launch_stage(int stage, int lat, bool delta, const SweepParams &p, double h,
+                        const void *X, const void *F, void *out, const void *coef,
+                        hipStream_t s);
+hipError_t set_stage_smem(int lat, bool delta, size_t bytes);
+
+// Auxiliary per-cell kernels (state conversions, moments); defined in aux.hip.
+hipError_t launch_set_state(const SweepParams &p, bool delta, const double *f, void *state,
+                            hipStream_t s);
+hipError_t launch_get_state(const SweepParams &p, bool delta, const void *state, double *f,
+                            int physical, hipStream_t s);
+hipError_t launch_init_eq(const SweepParams &p, bool delta, const double *rho, const double *ux,
+                          const double *uy, void *state, hipStream_t s);
+hipError_t launch_moments(const SweepParams &p, bool delta, const void *state, double *rho,
+                          double *ux, double *uy, int *bad, hipStream_t s);
+
+}  // namespace dk

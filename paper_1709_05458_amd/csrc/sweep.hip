@@ -1,0 +1,737 @@
+// Sweep kernels of the T3S3-DUGKS step for lattices whose velocities are
+// integer vectors times a scale (D2Q9 of the paper's "Discrete particle
+// velocities" section, and a D2Q37 lattice).  One kernel launch is one stage:
+//   STAGE 0 (stage A, steps (1)-(2)):  X = fhat(t_n)      -> out = tilde f(t')
+//   STAGE 1 (stage C, steps (3)-(4)):  X = tilde f(t'),
+//                                      F = fhat(t_n)      -> out = fhat(t_{n+1})
+//
+// Layout: SoA, element (q, cell) at q*ncell + cell, cell = j*nx + i.
+// A workgroup owns a tile of TX x TY cells, one cell per thread.  It stages
+// the pre-reconstruction variable B (eq. f_bar_1_6 for stage A, eq. fbp_5_12
+// for stage C) of every velocity over the tile plus a 2-cell halo in LDS.
+// The cell moments needed for B's equilibrium part are recomputed from the
+// loaded values, so no moment arrays are streamed.  Each thread then forms,
+// per velocity, the interface values at its four faces (eqs. interfaceEvof,
+// flux_DS), sums the interface moments over q in double, and keeps the part of
+// the micro-flux that is linear in the interface values; the equilibrium part
+// of the recovered interface distribution (eq. recover2f) is added once the
+// interface moments are complete.
+#include "dugks_internal.h"
+
+#include <utility>
+
+namespace dk {
+
+// ---------------------------------------------------------------------------
+// Lattices: velocity q = clat * (ex(q), ey(q)).
+// ---------------------------------------------------------------------------
+struct LatD2Q9 {
+    static constexpr int Q = 9;
+    static constexpr __host__ __device__ int ex(int q) { return q / 3 - 1; }
+    static constexpr __host__ __device__ int ey(int q) { return q % 3 - 1; }
+    static constexpr __host__ __device__ int opp(int q) { return 8 - q; }
+};
+
+struct LatD2Q37 {
+    static constexpr int Q = 37;
+    static constexpr __host__ __device__ int ex(int q)
+    {
+        constexpr int t[37] = {0, -1, 0, 0, 1, -1, -1, 1, 1, -2, 0, 0, 2, -2, -2, -1, -1, 1, 1,
+                               2, 2, -2, -2, 2, 2, -3, 0, 0, 3, -3, -3, -1, -1, 1, 1, 3, 3};
+        return t[q];
+    }
+    static constexpr __host__ __device__ int ey(int q)
+    {
+        constexpr int t[37] = {0, 0, -1, 1, 0, -1, 1, -1, 1, 0, -2, 2, 0, -1, 1, -2, 2, -2, 2,
+                               -1, 1, -2, 2, -2, 2, 0, -3, 3, 0, -1, 1, -3, 3, -3, 3, -1, 1};
+        return t[q];
+    }
+    static constexpr __host__ __device__ int opp(int q)
+    {
+        constexpr int t[37] = {0, 4, 3, 2, 1, 8, 7, 6, 5, 12, 11, 10, 9, 20, 19, 18, 17, 16, 15,
+                               14, 13, 24, 23, 22, 21, 28, 27, 26, 25, 36, 35, 34, 33, 32, 31, 30, 29};
+        return t[q];
+    }
+};
+
+__device__ __forceinline__ double fmaS(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaS(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+__device__ __forceinline__ int wrapi(int i, int n)
+{
+    i %= n;
+    return i < 0 ? i + n : i;
+}
+
+// Position in the (TX+4) x (TY+4) halo tile of load slot c: the first TX*TY
+// slots are the tile interior in thread order, the rest the 2-cell ring.
+__device__ __forceinline__ void halo_pos(int c, int TX, int TY, int &hx, int &hy)
+{
+    const int HX = TX + 4;
+    const int n0 = TX * TY;
+    if (c < n0) {
+        hx = c % TX + 2;
+        hy = c / TX + 2;
+        return;
+    }
+    int r = c - n0;
+    if (r < 2 * HX) { hy = r / HX; hx = r % HX; return; }
+    r -= 2 * HX;
+    if (r < 2 * HX) { hy = TY + 2 + r / HX; hx = r % HX; return; }
+    r -= 2 * HX;
+    if (r < 2 * TY) { hx = r & 1; hy = 2 + (r >> 1); return; }
+    r -= 2 * TY;
+    hx = TX + 2 + (r & 1);
+    hy = 2 + (r >> 1);
+}
+
+// Equilibrium of given physical moments in storage units, as coefficients of
+// the quadratic polynomial in the integer lattice vector e:
+//   E_q / s_q - r0 = c0 + c1x ex + c1y ey + c2xx ex^2 + c2xy ex ey + c2yy ey^2
+// (s_q = w_q, r0 = 0 for FP64 storage; s_q = 1, r0 = rho0 for FP32-delta).
+struct EPoly {
+    double c0, c1x, c1y, c2xx, c2xy, c2yy;
+};
+
+__device__ __forceinline__ EPoly epoly(double rho, double drho, double mx, double my,
+                                       double RT, double clat, bool delta)
+{
+    const double ir = 1.0 / rho, iRT = 1.0 / RT;
+    const double ux = mx * ir, uy = my * ir;
+    const double uu = ux * ux + uy * uy;
+    EPoly e;
+    e.c0 = (delta ? drho : rho) - 0.5 * rho * uu * iRT;
+    e.c1x = mx * iRT * clat;
+    e.c1y = my * iRT * clat;
+    const double k2 = 0.5 * rho * iRT * iRT * clat * clat;
+    e.c2xx = k2 * ux * ux;
+    e.c2xy = 2.0 * k2 * ux * uy;
+    e.c2yy = k2 * uy * uy;
+    return e;
+}
+
+template <class S>
+struct EPolyS {
+    S c0, c1x, c1y, c2xx, c2xy, c2yy;
+    __device__ __forceinline__ void set(const EPoly &e, double scale)
+    {
+        c0 = (S)(e.c0 * scale);
+        c1x = (S)(e.c1x * scale);
+        c1y = (S)(e.c1y * scale);
+        c2xx = (S)(e.c2xx * scale);
+        c2xy = (S)(e.c2xy * scale);
+        c2yy = (S)(e.c2yy * scale);
+    }
+    template <int EX, int EY>
+    __device__ __forceinline__ S eval() const
+    {
+        S v = c0;
+        if (EX) v = fmaS((S)EX, c1x, v);
+        if (EY) v = fmaS((S)EY, c1y, v);
+        if (EX) v = fmaS((S)(EX * EX), c2xx, v);
+        if (EX && EY) v = fmaS((S)(EX * EY), c2xy, v);
+        if (EY) v = fmaS((S)(EY * EY), c2yy, v);
+        return v;
+    }
+};
+
+// Physical moments from storage-unit sums (a0 = sum m_q x_q, ax = sum m_q ex x_q, ...).
+__device__ __forceinline__ void phys_moments(const SweepParams &p, bool delta, double a0,
+                                             double ax, double ay, double &rho, double &drho,
+                                             double &mx, double &my)
+{
+    if (delta) {
+        drho = p.rho0 * p.M0m1 + a0;
+        rho = p.rho0 + drho;
+        mx = p.rho0 * p.M1x + p.clat * ax;
+        my = p.rho0 * p.M1y + p.clat * ay;
+    } else {
+        rho = a0;
+        drho = a0;
+        mx = p.clat * ax;
+        my = p.clat * ay;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// General-path expansion about one cell (derivative form of eq. flux_DS with
+// per-cell 3-point weights; one-sided next to walls, Lagrange on non-uniform
+// grids).  P points at the LDS plane, (hx, hy) is the upwind cell's position
+// in the halo tile and (gi, gj) its global index.
+// ---------------------------------------------------------------------------
+template <class S>
+__device__ __forceinline__ double expand_general(const SweepParams &p, const S *P, int HX, int hx,
+                                                 int hy, int gi, int gj, double dx, double dy)
+{
+    const int ox = p.g.sx_off[gi], oy = p.g.sy_off[gj];
+    const double *d1x = p.g.sx_d1 + 3 * gi, *d2x = p.g.sx_d2 + 3 * gi;
+    const double *d1y = p.g.sy_d1 + 3 * gj, *d2y = p.g.sy_d2 + 3 * gj;
+    double Bx = 0, Bxx = 0, By = 0, Byy = 0, Bxy = 0;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const double v = (double)P[hy * HX + hx + ox + k];
+        Bx = __builtin_fma(d1x[k], v, Bx);
+        Bxx = __builtin_fma(d2x[k], v, Bxx);
+    }
+#pragma unroll
+    for (int l = 0; l < 3; l++) {
+        const double v = (double)P[(hy + oy + l) * HX + hx];
+        By = __builtin_fma(d1y[l], v, By);
+        Byy = __builtin_fma(d2y[l], v, Byy);
+    }
+#pragma unroll
+    for (int l = 0; l < 3; l++) {
+        double row = 0;
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+            row = __builtin_fma(d1x[k], (double)P[(hy + oy + l) * HX + hx + ox + k], row);
+        Bxy = __builtin_fma(d1y[l], row, Bxy);
+    }
+    const double B0 = (double)P[hy * HX + hx];
+    const double quad = dx * dx * Bxx + 2.0 * dx * dy * Bxy + dy * dy * Byy;
+    return B0 + dx * Bx + dy * By + p.kappa * quad;
+}
+
+// ---------------------------------------------------------------------------
+// Per-thread state of one stage sweep.
+// ---------------------------------------------------------------------------
+template <class Lat, class S, bool DELTA>
+struct ThreadState {
+    static constexpr int Q = Lat::Q;
+    S La[Q];          // linear part of the micro-flux
+    S R[Q];           // own-cell part of the stage output
+    double mr[4], mx[4], my[4];   // interface moment sums (storage units) W,E,S,N
+    double num[4];                // diffuse walls: arriving flux sums
+    S aw, ae, as_, an;            // recovery weights alpha of the four faces
+    S cx, cy;                     // -1/dx, -1/dy of the own cell
+};
+
+template <class Lat, class S, bool DELTA, int q>
+__device__ __forceinline__ void accumulate(ThreadState<Lat, S, DELTA> &t, int face, S v, double wq)
+{
+    constexpr int EX = Lat::ex(q), EY = Lat::ey(q);
+    const double d = DELTA ? wq * (double)v : (double)v;
+    t.mr[face] += d;
+    if (EX) t.mx[face] = __builtin_fma((double)EX, d, t.mx[face]);
+    if (EY) t.my[face] = __builtin_fma((double)EY, d, t.my[face]);
+}
+
+// Fast path: uniform grid, tile away from walls.  coef[q*24 + 0..11] are the
+// x-face weights over cells (i-2..i+1) x (j-1..j+1) of face i (between cells
+// i-1 and i), coef[q*24 + 12..23] the y-face weights over (i-1..i+1) x
+// (j-2..j+1) of face j; they fold the upwind choice, the characteristic foot
+// point and the 3-point derivatives into one linear combination.
+template <class Lat, class S, bool DELTA, int q>
+__device__ __forceinline__ void faces_fast(ThreadState<Lat, S, DELTA> &t, const S *lds, int plane,
+                                           int HX, int base, const S *__restrict__ coef,
+                                           double wq, S xq_s, S yq_s)
+{
+    constexpr int EX = Lat::ex(q), EY = Lat::ey(q);
+    const S *P = lds + q * plane + base;
+    const S *C = coef + q * 24;
+    S vw = 0, ve = 0, vs = 0, vn = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        if ((EX > 0 && k == 3) || (EX < 0 && k == 0)) continue;
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            const S c = C[k * 3 + b];
+            vw = fmaS(c, P[(b - 1) * HX + (k - 2)], vw);
+            ve = fmaS(c, P[(b - 1) * HX + (k - 1)], ve);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        if ((EY > 0 && k == 3) || (EY < 0 && k == 0)) continue;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            const S c = C[12 + k * 3 + a];
+            vs = fmaS(c, P[(k - 2) * HX + (a - 1)], vs);
+            vn = fmaS(c, P[(k - 1) * HX + (a - 1)], vn);
+        }
+    }
+    accumulate<Lat, S, DELTA, q>(t, 0, vw, wq);
+    accumulate<Lat, S, DELTA, q>(t, 1, ve, wq);
+    accumulate<Lat, S, DELTA, q>(t, 2, vs, wq);
+    accumulate<Lat, S, DELTA, q>(t, 3, vn, wq);
+    S l = 0;
+    if (EX) l = fmaS(xq_s * t.cx, t.ae * ve - t.aw * vw, l);
+    if (EY) l = fmaS(yq_s * t.cy, t.an * vn - t.as_ * vs, l);
+    t.La[q] = l;
+    // keep the scheduler from hoisting the next velocity's loads above this
+    // one (that raises register pressure far beyond what the data needs)
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// General path (walls, non-uniform spacing).  Face values are formed in
+// double from the LDS plane(s).  Leaving velocities at a diffuse wall are
+// deferred until the wall density is known.
+template <class Lat, class S, bool DELTA, int q>
+__device__ __forceinline__ void faces_general(ThreadState<Lat, S, DELTA> &t, const SweepParams &p,
+                                              const S *lds, int plane, int HX, int hxo, int hyo,
+                                              int i, int j, double h, double rho_own, double wq,
+                                              S xq_s, S yq_s)
+{
+    constexpr int EX = Lat::ex(q), EY = Lat::ey(q);
+    constexpr int O = Lat::opp(q);
+    constexpr int OX = Lat::ex(O), OY = Lat::ey(O);
+    const double cl = p.clat;
+    const double xq = cl * EX, yq = cl * EY;
+    const S *P = lds + q * plane;
+    const S *PO = lds + O * plane;
+    const int nx = p.nx, ny = p.ny;
+    double v[4];
+    bool defer[4] = {false, false, false, false};
+
+    // ---- x-faces: W = face i (cells i-1 | i), E = face i+1 ----
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+        const int fi = i + s;
+        const int hxr = hxo + s;   // LDS column of cell fi
+        const double dy = -yq * h;
+        double val = 0.0;
+        if (!p.perx && fi == 0) {
+            if (EX <= 0) {
+                val = expand_general(p, P, HX, hxr, hyo, 0, j, p.g.dxr[0] - xq * h, dy);
+            } else if (p.bc[0] == 1) {
+                const double bb = 2.0 * rho_own * (xq * p.uw[0][0] + yq * p.uw[0][1]) / p.RT;
+                val = expand_general(p, PO, HX, hxr, hyo, 0, j, p.g.dxr[0] - cl * OX * h, -cl * OY * h) +
+                      (DELTA ? bb : wq * bb);
+            } else {
+                defer[s] = true;
+            }
+            if (EX < 0) {   // arriving at the west wall: xi.n = -xi_x > 0
+                t.num[0] += -xq * (DELTA ? wq * val : val);
+            }
+        } else if (!p.perx && fi == nx) {
+            if (EX >= 0) {
+                val = expand_general(p, P, HX, hxr - 1, hyo, nx - 1, j, p.g.dxl[nx] - xq * h, dy);
+            } else if (p.bc[1] == 1) {
+                const double bb = 2.0 * rho_own * (xq * p.uw[1][0] + yq * p.uw[1][1]) / p.RT;
+                val = expand_general(p, PO, HX, hxr - 1, hyo, nx - 1, j, p.g.dxl[nx] - cl * OX * h,
+                                     -cl * OY * h) +
+                      (DELTA ? bb : wq * bb);
+            } else {
+                defer[s] = true;
+            }
+            if (EX > 0) t.num[1] += xq * (DELTA ? wq * val : val);
+        } else {
+            const int giL = wrapi(fi - 1, nx), giR = wrapi(fi, nx);
+            if (EX > 0) {
+                val = expand_general(p, P, HX, hxr - 1, hyo, giL, j, p.g.dxl[fi] - xq * h, dy);
+            } else if (EX < 0) {
+                val = expand_general(p, P, HX, hxr, hyo, giR, j, p.g.dxr[fi] - xq * h, dy);
+            } else {
+                const double a = expand_general(p, P, HX, hxr - 1, hyo, giL, j, p.g.dxl[fi], dy);
+                const double b = expand_general(p, P, HX, hxr, hyo, giR, j, p.g.dxr[fi], dy);
+                val = 0.5 * (a + b);
+            }
+        }
+        v[s] = val;
+    }
+    // ---- y-faces: S = face j (cells j-1 | j), N = face j+1 ----
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+        const int fj = j + s;
+        const int hyr = hyo + s;
+        const double dx = -xq * h;
+        double val = 0.0;
+        if (!p.pery && fj == 0) {
+            if (EY <= 0) {
+                val = expand_general(p, P, HX, hxo, hyr, i, 0, dx, p.g.dyr[0] - yq * h);
+            } else if (p.bc[2] == 1) {
+                const double bb = 2.0 * rho_own * (xq * p.uw[2][0] + yq * p.uw[2][1]) / p.RT;
+                val = expand_general(p, PO, HX, hxo, hyr, i, 0, -cl * OX * h, p.g.dyr[0] - cl * OY * h) +
+                      (DELTA ? bb : wq * bb);
+            } else {
+                defer[2 + s] = true;
+            }
+            if (EY < 0) t.num[2] += -yq * (DELTA ? wq * val : val);
+        } else if (!p.pery && fj == ny) {
+            if (EY >= 0) {
+                val = expand_general(p, P, HX, hxo, hyr - 1, i, ny - 1, dx, p.g.dyl[ny] - yq * h);
+            } else if (p.bc[3] == 1) {
+                const double bb = 2.0 * rho_own * (xq * p.uw[3][0] + yq * p.uw[3][1]) / p.RT;
+                val = expand_general(p, PO, HX, hxo, hyr - 1, i, ny - 1, -cl * OX * h,
+                                     p.g.dyl[ny] - cl * OY * h) +
+                      (DELTA ? bb : wq * bb);
+            } else {
+                defer[2 + s] = true;
+            }
+            if (EY > 0) t.num[3] += yq * (DELTA ? wq * val : val);
+        } else {
+            const int gjS = wrapi(fj - 1, ny), gjN = wrapi(fj, ny);
+            if (EY > 0) {
+                val = expand_general(p, P, HX, hxo, hyr - 1, i, gjS, dx, p.g.dyl[fj] - yq * h);
+            } else if (EY < 0) {
+                val = expand_general(p, P, HX, hxo, hyr, i, gjN, dx, p.g.dyr[fj] - yq * h);
+            } else {
+                const double a = expand_general(p, P, HX, hxo, hyr - 1, i, gjS, dx, p.g.dyl[fj]);
+                const double b = expand_general(p, P, HX, hxo, hyr, i, gjN, dx, p.g.dyr[fj]);
+                val = 0.5 * (a + b);
+            }
+        }
+        v[2 + s] = val;
+    }
+    const S vw = (S)v[0], ve = (S)v[1], vs = (S)v[2], vn = (S)v[3];
+    if (!defer[0]) accumulate<Lat, S, DELTA, q>(t, 0, vw, wq);
+    if (!defer[1]) accumulate<Lat, S, DELTA, q>(t, 1, ve, wq);
+    if (!defer[2]) accumulate<Lat, S, DELTA, q>(t, 2, vs, wq);
+    if (!defer[3]) accumulate<Lat, S, DELTA, q>(t, 3, vn, wq);
+    S l = 0;
+    if (EX) l = fmaS(xq_s * t.cx, t.ae * ve - t.aw * vw, l);
+    if (EY) l = fmaS(yq_s * t.cy, t.an * vn - t.as_ * vs, l);
+    t.La[q] = l;
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+template <class Lat, class S, bool DELTA, int q>
+__device__ __forceinline__ void load_q(const S *__restrict__ X, long long n, long long cell, S *v)
+{
+    v[q] = X[q * n + cell];
+}
+
+template <class Lat, class S, bool DELTA, int q>
+__device__ __forceinline__ void moment_q(const S *v, double wq, double &a0, double &ax, double &ay)
+{
+    constexpr int EX = Lat::ex(q), EY = Lat::ey(q);
+    const double d = DELTA ? wq * (double)v[q] : (double)v[q];
+    a0 += d;
+    if (EX) ax = __builtin_fma((double)EX, d, ax);
+    if (EY) ay = __builtin_fma((double)EY, d, ay);
+}
+
+// ---------------------------------------------------------------------------
+// The stage kernel.  GENERAL = false handles tiles of a uniform grid that are
+// clear of walls (precomputed face weights); GENERAL = true handles the other
+// tiles (walls, one-sided stencils, non-uniform spacing).  Each instance
+// returns at once on the tiles of the other kind.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool tile_is_fast(const SweepParams &p, int i0, int j0, int TX, int TY)
+{
+    return p.uniform && (p.perx || (i0 >= 2 && i0 + TX <= p.nx - 2)) &&
+           (p.pery || (j0 >= 2 && j0 + TY <= p.ny - 2));
+}
+
+template <class Lat, class S, bool DELTA, int STAGE, bool GENERAL>
+__global__ void __launch_bounds__(512)
+sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
+            const S *__restrict__ F, S *__restrict__ out, const S *__restrict__ coef)
+{
+    constexpr int Q = Lat::Q;
+    using Seq = std::make_integer_sequence<int, Q>;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    S *lds = reinterpret_cast<S *>(smem_raw);
+
+    const int TX = p.tile_x, TY = p.tile_y;
+    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    if (tile_is_fast(p, i0, j0, TX, TY) == GENERAL) return;   // whole block: no barrier skipped
+
+    const int HX = TX + 4;
+    const int plane = HX * (TY + 4);
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int lx = tid % TX, ly = tid / TX;
+    const int i = i0 + lx, j = j0 + ly;
+    const bool valid = (i < p.nx) && (j < p.ny);
+    const long long n = p.ncell;
+    const double dt = p.dt, RT = p.RT, cl = p.clat;
+    const double *__restrict__ W = p.w;
+    const long long ocell = (long long)j * p.nx + i;
+    const double tau_o = (p.tau_field && valid) ? p.tau[ocell] : p.tau0;
+    const double c1 = (12.0 * tau_o - dt) / (12.0 * tau_o + 3.0 * dt);
+    const double e1 = 4.0 * dt / (12.0 * tau_o + 3.0 * dt);
+
+    ThreadState<Lat, S, DELTA> t;
+    double o_rho = 1.0;
+
+    // ---- load phase: B over tile + halo; the first slot of every thread is
+    //      its own cell, whose share of the stage output R is formed here ----
+    for (int c = tid; c < plane; c += nthr) {
+        int hx, hy;
+        halo_pos(c, TX, TY, hx, hy);
+        int gi = i0 + hx - 2, gj = j0 + hy - 2;
+        bool in = true;
+        if (p.perx) gi = wrapi(gi, p.nx); else in = in && gi >= 0 && gi < p.nx;
+        if (p.pery) gj = wrapi(gj, p.ny); else in = in && gj >= 0 && gj < p.ny;
+        S v[Q];
+        double a0 = 0, ax = 0, ay = 0;
+        const long long cell = (long long)gj * p.nx + gi;
+        if (in) {
+            [&]<int... qs>(std::integer_sequence<int, qs...>) {
+                (load_q<Lat, S, DELTA, qs>(X, n, cell, v), ...);
+                (moment_q<Lat, S, DELTA, qs>(v, W[qs], a0, ax, ay), ...);
+            }(Seq{});
+        } else {
+#pragma unroll
+            for (int q = 0; q < Q; q++) v[q] = (S)0;
+            a0 = DELTA ? 0.0 : 1.0;
+        }
+        double rho, drho, mx, my;
+        phys_moments(p, DELTA, a0, ax, ay, rho, drho, mx, my);
+        if (!in) { rho = 1.0; drho = DELTA ? 0.0 : 1.0; mx = my = 0.0; }
+        const double tau = (p.tau_field && in) ? p.tau[cell] : p.tau0;
+        double cc, ce;
+        if (STAGE == 0) {   // eq. f_bar_1_6
+            cc = (12.0 * tau - dt) / (12.0 * tau + 3.0 * dt);
+            ce = 4.0 * dt / (12.0 * tau + 3.0 * dt);
+        } else if (p.literal_fbp) {   // eq. fbp_5_12 as printed
+            cc = (24.0 * tau - 5.0 * dt) / (24.0 * tau + 10.0 * dt);
+            ce = 15.0 * dt / (24.0 * tau + 10.0 * dt);
+        } else {   // eq. fbp_5_12 with the coefficients that map tilde f onto fbar^{+,5dt/12}
+            cc = (24.0 * tau - 5.0 * dt) / (24.0 * tau + 4.0 * dt);
+            ce = 9.0 * dt / (24.0 * tau + 4.0 * dt);
+        }
+        const EPoly ep_cell = epoly(rho, drho, mx, my, RT, cl, DELTA);
+        EPolyS<S> e;
+        e.set(ep_cell, ce);
+        const S ccs = (S)cc;
+        S *dst = lds + hy * HX + hx;
+        [&]<int... qs>(std::integer_sequence<int, qs...>) {
+            ((dst[qs * plane] = fmaS(ccs, v[qs],
+                                     DELTA ? e.template eval<Lat::ex(qs), Lat::ey(qs)>()
+                                           : (S)W[qs] * e.template eval<Lat::ex(qs), Lat::ey(qs)>())),
+             ...);
+        }(Seq{});
+        if (c == tid && valid) {
+            o_rho = rho;
+            if (STAGE == 0) {
+                // tilde f^+(t_n) = 5/4 fbar^{+,dt/6} - 1/4 fhat  (eq. f_tilde_1_3)
+                EPolyS<S> en;
+                en.set(ep_cell, 1.25 * e1);
+                const S kx = (S)(1.25 * c1 - 0.25);
+                [&]<int... qs>(std::integer_sequence<int, qs...>) {
+                    ((t.R[qs] = fmaS(kx, v[qs],
+                                     DELTA ? en.template eval<Lat::ex(qs), Lat::ey(qs)>()
+                                           : (S)W[qs] * en.template eval<Lat::ex(qs), Lat::ey(qs)>())),
+                     ...);
+                }(Seq{});
+            } else {
+                // fhat(t_{n+1}) = fhat/4 + 3/4 fbar^{+,dt/6} + 3/4 dt Omega(t') + 9/7 (tilde f(t') -
+                // tilde f^+(t_n)) + 4 dt/7 L**  (eqs. fhp, collisionterm, feqIntD3rdHat2_DS; the T2
+                // update of step 2 gives 3 dt/7 L* = 9/7 (tilde f(t') - tilde f^+(t_n)))
+                S fh[Q];
+                double b0 = 0, bx = 0, by = 0;
+                [&]<int... qs>(std::integer_sequence<int, qs...>) {
+                    (load_q<Lat, S, DELTA, qs>(F, n, ocell, fh), ...);
+                    (moment_q<Lat, S, DELTA, qs>(fh, W[qs], b0, bx, by), ...);
+                }(Seq{});
+                double rn, drn, mxn, myn;
+                phys_moments(p, DELTA, b0, bx, by, rn, drn, mxn, myn);
+                const double kw = 6.0 * dt / (6.0 * tau_o + dt);
+                const double a_f = (4.0 - 6.0 * c1) / 7.0;
+                const double a_En = -6.0 / 7.0 * e1;
+                const double a_G = 9.0 / 7.0 - 0.75 * kw;
+                const double a_Ep = 0.75 * kw;
+                EPolyS<S> en, ep;
+                en.set(epoly(rn, drn, mxn, myn, RT, cl, DELTA), a_En);
+                ep.set(ep_cell, a_Ep);
+                const S sf = (S)a_f, sg = (S)a_G;
+                [&]<int... qs>(std::integer_sequence<int, qs...>) {
+                    ((t.R[qs] = fmaS(sf, fh[qs], fmaS(sg, v[qs],
+                        (DELTA ? (S)1 : (S)W[qs]) *
+                            (en.template eval<Lat::ex(qs), Lat::ey(qs)>() +
+                             ep.template eval<Lat::ex(qs), Lat::ey(qs)>())))),
+                     ...);
+                }(Seq{});
+            }
+            if (GENERAL) {   // park R in the output to free registers for the general path
+#pragma unroll
+                for (int q = 0; q < Q; q++) out[q * n + ocell] = t.R[q];
+            }
+        }
+    }
+    __syncthreads();
+    if (!valid) return;   // no further barrier below
+    const S aL = (S)(STAGE == 0 ? dt / 3.0 : 4.0 * dt / 7.0);
+
+    // ---- interface recovery weights of the four faces (eq. recover2f) -------
+    double tb[4];
+    if (p.tau_field) {
+        const int im = p.perx ? wrapi(i - 1, p.nx) : (i > 0 ? i - 1 : i);
+        const int ip = p.perx ? wrapi(i + 1, p.nx) : (i < p.nx - 1 ? i + 1 : i);
+        const int jm = p.pery ? wrapi(j - 1, p.ny) : (j > 0 ? j - 1 : j);
+        const int jp = p.pery ? wrapi(j + 1, p.ny) : (j < p.ny - 1 ? j + 1 : j);
+        tb[0] = 0.5 * (tau_o + p.tau[(long long)j * p.nx + im]);
+        tb[1] = 0.5 * (tau_o + p.tau[(long long)j * p.nx + ip]);
+        tb[2] = 0.5 * (tau_o + p.tau[(long long)jm * p.nx + i]);
+        tb[3] = 0.5 * (tau_o + p.tau[(long long)jp * p.nx + i]);
+    } else {
+        tb[0] = tb[1] = tb[2] = tb[3] = p.tau0;
+    }
+    double alpha[4], beta[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        alpha[k] = 2.0 * tb[k] / (2.0 * tb[k] + h);
+        beta[k] = h / (2.0 * tb[k] + h);
+    }
+    t.aw = (S)alpha[0]; t.ae = (S)alpha[1]; t.as_ = (S)alpha[2]; t.an = (S)alpha[3];
+    const double idx = p.uniform ? p.inv_dx : p.g.inv_dx[i];
+    const double idy = p.uniform ? p.inv_dy : p.g.inv_dy[j];
+    t.cx = (S)(-idx);
+    t.cy = (S)(-idy);
+#pragma unroll
+    for (int k = 0; k < 4; k++) { t.mr[k] = t.mx[k] = t.my[k] = 0.0; t.num[k] = 0.0; }
+
+    // ---- interface values, moments and linear flux part, all q --------------
+    const S cls = (S)cl;
+    if (!GENERAL) {
+        const int base = (ly + 2) * HX + (lx + 2);
+        [&]<int... qs>(std::integer_sequence<int, qs...>) {
+            (faces_fast<Lat, S, DELTA, qs>(t, lds, plane, HX, base, coef, W[qs],
+                                           cls * (S)Lat::ex(qs), cls * (S)Lat::ey(qs)), ...);
+        }(Seq{});
+    } else {
+        [&]<int... qs>(std::integer_sequence<int, qs...>) {
+            (faces_general<Lat, S, DELTA, qs>(t, p, lds, plane, HX, lx + 2, ly + 2, i, j, h, o_rho,
+                                              W[qs], cls * (S)Lat::ex(qs), cls * (S)Lat::ey(qs)),
+             ...);
+        }(Seq{});
+    }
+
+    // ---- diffuse walls: wall density from zero net mass flux ---------------
+    double rw[4] = {0, 0, 0, 0};
+    bool dsf[4];
+    dsf[0] = GENERAL && !p.perx && i == 0 && p.bc[0] == 2;
+    dsf[1] = GENERAL && !p.perx && i == p.nx - 1 && p.bc[1] == 2;
+    dsf[2] = GENERAL && !p.pery && j == 0 && p.bc[2] == 2;
+    dsf[3] = GENERAL && !p.pery && j == p.ny - 1 && p.bc[3] == 2;
+    double M[4][3];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        M[k][0] = t.mr[k];
+        M[k][1] = t.mx[k];
+        M[k][2] = t.my[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        // physical moments of face k
+        double rho, drho, mx, my;
+        phys_moments(p, DELTA, M[k][0], M[k][1], M[k][2], rho, drho, mx, my);
+        if (GENERAL && dsf[k]) {
+            rw[k] = (t.num[k] + p.ds_num_off[k]) / p.ds_den[k];
+            const double r0 = DELTA ? p.rho0 : 0.0;
+            rho += rw[k] * p.ds_m[k][0] - r0 * p.ds_w[k][0];
+            drho += rw[k] * p.ds_m[k][0] - r0 * p.ds_w[k][0];
+            mx += rw[k] * p.ds_m[k][1] - r0 * p.ds_w[k][1];
+            my += rw[k] * p.ds_m[k][2] - r0 * p.ds_w[k][2];
+        }
+        M[k][0] = rho; M[k][1] = drho; M[k][2] = mx;
+        // reuse slot: store my in t.my
+        t.my[k] = my;
+    }
+    // equilibrium part beta_b E_b of the recovered interface values, as
+    // east-minus-west and north-minus-south polynomials
+    EPolyS<S> dEx, dEy;
+    {
+        const EPoly ew = epoly(M[0][0], M[0][1], M[0][2], t.my[0], RT, cl, DELTA);
+        const EPoly ee = epoly(M[1][0], M[1][1], M[1][2], t.my[1], RT, cl, DELTA);
+        const EPoly es = epoly(M[2][0], M[2][1], M[2][2], t.my[2], RT, cl, DELTA);
+        const EPoly en = epoly(M[3][0], M[3][1], M[3][2], t.my[3], RT, cl, DELTA);
+        EPoly dx, dy;
+        dx.c0 = beta[1] * ee.c0 - beta[0] * ew.c0;
+        dx.c1x = beta[1] * ee.c1x - beta[0] * ew.c1x;
+        dx.c1y = beta[1] * ee.c1y - beta[0] * ew.c1y;
+        dx.c2xx = beta[1] * ee.c2xx - beta[0] * ew.c2xx;
+        dx.c2xy = beta[1] * ee.c2xy - beta[0] * ew.c2xy;
+        dx.c2yy = beta[1] * ee.c2yy - beta[0] * ew.c2yy;
+        dy.c0 = beta[3] * en.c0 - beta[2] * es.c0;
+        dy.c1x = beta[3] * en.c1x - beta[2] * es.c1x;
+        dy.c1y = beta[3] * en.c1y - beta[2] * es.c1y;
+        dy.c2xx = beta[3] * en.c2xx - beta[2] * es.c2xx;
+        dy.c2xy = beta[3] * en.c2xy - beta[2] * es.c2xy;
+        dy.c2yy = beta[3] * en.c2yy - beta[2] * es.c2yy;
+        dEx.set(dx, 1.0);
+        dEy.set(dy, 1.0);
+    }
+    const bool anyds = GENERAL && (dsf[0] || dsf[1] || dsf[2] || dsf[3]);
+    const S r0s = (S)(DELTA ? p.rho0 : 0.0);
+    const int nq = Q;
+
+    // ---- finish: L = La + equilibrium part (+ deferred wall terms); output --
+    [&]<int... qs>(std::integer_sequence<int, qs...>) {
+        (([&] {
+             constexpr int q = qs;
+             constexpr int EX = Lat::ex(q), EY = Lat::ey(q);
+             const S xq = cls * (S)EX, yq = cls * (S)EY;
+             S L = t.La[q];
+             const S sq = DELTA ? (S)1 : (S)W[q];
+             if (EX) L = fmaS(xq * t.cx, sq * dEx.template eval<EX, EY>(), L);
+             if (EY) L = fmaS(yq * t.cy, sq * dEy.template eval<EX, EY>(), L);
+             if (GENERAL && anyds) {
+                 // leaving velocities of diffuse walls: fbar = E(rho_w, u_w)
+                 if (EX > 0 && dsf[0]) L = fmaS(-(xq * t.cx) * t.aw, (S)rw[0] * (S)p.wall_E[0 * nq + q] - r0s, L);
+                 if (EX < 0 && dsf[1]) L = fmaS((xq * t.cx) * t.ae, (S)rw[1] * (S)p.wall_E[1 * nq + q] - r0s, L);
+                 if (EY > 0 && dsf[2]) L = fmaS(-(yq * t.cy) * t.as_, (S)rw[2] * (S)p.wall_E[2 * nq + q] - r0s, L);
+                 if (EY < 0 && dsf[3]) L = fmaS((yq * t.cy) * t.an, (S)rw[3] * (S)p.wall_E[3 * nq + q] - r0s, L);
+             }
+             const S Rq = GENERAL ? out[q * n + ocell] : t.R[q];
+             out[q * n + ocell] = fmaS(aL, L, Rq);
+         }()),
+         ...);
+    }(Seq{});
+}
+
+// ---------------------------------------------------------------------------
+// Host launchers
+// ---------------------------------------------------------------------------
+template <class Lat, class S, bool DELTA, int STAGE>
+static hipError_t launch_t(const SweepParams &p, double h, const void *X, const void *F, void *out,
+                           const void *coef, hipStream_t s)
+{
+    dim3 grid((p.nx + p.tile_x - 1) / p.tile_x, (p.ny + p.tile_y - 1) / p.tile_y);
+    dim3 block(p.tile_x * p.tile_y);
+    size_t smem = sizeof(S) * Lat::Q * (size_t)(p.tile_x + 4) * (p.tile_y + 4);
+    // tiles of the fast kind exist unless the grid is non-uniform; tiles of the
+    // general kind exist unless the domain is uniform and fully periodic
+    const bool any_fast = p.uniform;
+    const bool any_general = !(p.uniform && p.perx && p.pery);
+    if (any_fast)
+        hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, false>), grid, block, smem, s, p, h,
+                           (const S *)X, (const S *)F, (S *)out, (const S *)coef);
+    if (any_general)
+        hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, true>), grid, block, smem, s, p, h,
+                           (const S *)X, (const S *)F, (S *)out, (const S *)coef);
+    return hipGetLastError();
+}
+
+template <class Lat, class S, bool DELTA>
+static hipError_t smem_t(size_t bytes)
+{
+    const void *fns[4] = {(const void *)sweep_small<Lat, S, DELTA, 0, false>,
+                          (const void *)sweep_small<Lat, S, DELTA, 1, false>,
+                          (const void *)sweep_small<Lat, S, DELTA, 0, true>,
+                          (const void *)sweep_small<Lat, S, DELTA, 1, true>};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t set_stage_smem(int lat, bool delta, size_t bytes)
+{
+    if (lat == 9) return delta ? smem_t<LatD2Q9, float, true>(bytes) : smem_t<LatD2Q9, double, false>(bytes);
+    if (lat == 37) return delta ? smem_t<LatD2Q37, float, true>(bytes) : smem_t<LatD2Q37, double, false>(bytes);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_stage(int stage, int lat, bool delta, const SweepParams &p, double h,
+                        const void *X, const void *F, void *out, const void *coef, hipStream_t s)
+{
+#define DUGKS_L(LAT, S_, D_)                                                              \
+    return stage == 0 ? launch_t<LAT, S_, D_, 0>(p, h, X, F, out, coef, s)               \
+                      : launch_t<LAT, S_, D_, 1>(p, h, X, F, out, coef, s)
+    if (lat == 9) {
+        if (delta) DUGKS_L(LatD2Q9, float, true);
+        DUGKS_L(LatD2Q9, double, false);
+    }
+    if (lat == 37) {
+        if (delta) DUGKS_L(LatD2Q37, float, true);
+        DUGKS_L(LatD2Q37, double, false);
+    }
+#undef DUGKS_L
+    return hipErrorInvalidValue;
+}
+
+}  // namespace dk

@@ -1,0 +1,243 @@
+"""Python binding of libdugks.so (argument marshalling only).
+
+Every step of the sweep runs in the HIP kernels of the library; this module
+only turns numpy arrays / torch tensors into pointers and checks status codes.
+If the library is not built, importing it raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdugks.so")
+
+FP64, FP32_DELTA = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+ALLOW_MOMENT_DEFECT = 1
+K_STAGE_A, K_STAGE_C, K_AUX = 0, 1, 2
+
+STATUS = {0: "DUGKS_OK", -1: "DUGKS_EINVAL", -2: "DUGKS_EUNSTABLE", -3: "DUGKS_EMOMENT",
+          -4: "DUGKS_ENOMEM", -5: "DUGKS_EDEVICE", -6: "DUGKS_ENONFINITE", -7: "DUGKS_ENOTSUP"}
+
+
+class DugksError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str):
+        super().__init__(f"{what}: {STATUS.get(code, code)} ({detail})")
+        self.code = code
+
+
+class DugksDesc(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int),
+                ("xf", POINTER(c_double)), ("yf", POINTER(c_double)),
+                ("nq", c_int),
+                ("xi", POINTER(c_double)), ("w", POINTER(c_double)),
+                ("RT", c_double), ("dt", c_double),
+                ("tau", POINTER(c_double)), ("tau0", c_double),
+                ("bc", c_int * 4), ("u_wall", (c_double * 2) * 4),
+                ("precision", c_int), ("rho0", c_double), ("taylor_quad", c_double),
+                ("stream", c_void_p), ("flags", c_int),
+                ("tile_x", c_int), ("tile_y", c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdugks.so; raise if it is missing (build it with __graft_entry__.build())."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, ip, dp = c_void_p, c_int, POINTER(c_double)
+        sig = {
+            "dugks_create": ([POINTER(DugksDesc), POINTER(c_void_p)], ip),
+            "dugks_destroy": ([vp], ip),
+            "dugks_set_state": ([vp, vp, ip], ip),
+            "dugks_init_equilibrium": ([vp, vp, vp, vp, ip], ip),
+            "dugks_step": ([vp, ip], ip),
+            "dugks_moments": ([vp, vp, vp, vp, ip], ip),
+            "dugks_get_state": ([vp, vp, ip], ip),
+            "dugks_get_fhat": ([vp, vp, ip], ip),
+            "dugks_set_tau": ([vp, vp, ip], ip),
+            "dugks_sync": ([vp], ip),
+            "dugks_backward": ([vp, vp, ip, ip, vp, vp, vp, vp, ip], ip),
+            "dugks_prof_begin": ([vp, ip], ip),
+            "dugks_prof_query": ([vp, ip, dp, POINTER(c_int)], ip),
+            "dugks_prof_end": ([vp], ip),
+            "dugks_describe": ([vp, c_char_p, ip], ip),
+            "dugks_strerror": ([ip], c_char_p),
+            "dugks_last_error_message": ([], c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().dugks_last_error_message().decode()
+        raise DugksError(rc, what, msg)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(POINTER(c_double))
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr_mem(x, dtype=np.float64):
+    """(pointer, mem kind, keep-alive) of a numpy array or torch tensor."""
+    if _is_torch(x):
+        import torch
+        if x.dtype != torch.float64 or not x.is_contiguous():
+            raise TypeError("torch tensors passed to the library must be contiguous float64")
+        return c_void_p(x.data_ptr()), (MEM_DEVICE if x.is_cuda else MEM_HOST), x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return c_void_p(a.ctypes.data), MEM_HOST, a
+
+
+class Solver:
+    """One T3S3-DUGKS solver instance (a dugks_t handle)."""
+
+    def __init__(self, case, precision: int = FP64, taylor_quad: float = 1.0, stream=None,
+                 tile=None, allow_defect: bool = False, tau=None):
+        g, vs = case.grid, case.vs
+        self.case = case
+        self.nx, self.ny, self.nq = g.nx, g.ny, vs.nq
+        self.ncell = g.nx * g.ny
+        self._keep = [np.ascontiguousarray(g.xf, dtype=np.float64),
+                      np.ascontiguousarray(g.yf, dtype=np.float64),
+                      np.ascontiguousarray(vs.xi.reshape(-1), dtype=np.float64),
+                      np.ascontiguousarray(vs.w, dtype=np.float64)]
+        d = DugksDesc()
+        d.nx, d.ny, d.nq = g.nx, g.ny, vs.nq
+        d.xf, d.yf = _dptr(self._keep[0]), _dptr(self._keep[1])
+        d.xi, d.w = _dptr(self._keep[2]), _dptr(self._keep[3])
+        d.RT, d.dt = vs.RT, case.dt
+        tau = case.tau if tau is None else tau
+        tau = np.asarray(tau, dtype=np.float64)
+        if tau.ndim == 0 or np.ptp(tau) == 0.0:
+            d.tau = POINTER(c_double)()
+            d.tau0 = float(tau.reshape(-1)[0])
+            self.tau_field = False
+        else:
+            t = np.ascontiguousarray(tau.reshape(-1))
+            self._keep.append(t)
+            d.tau = _dptr(t)
+            d.tau0 = float(t.mean())
+            self.tau_field = True
+        for k in range(4):
+            d.bc[k] = int(case.bc[k])
+            d.u_wall[k][0] = float(case.u_wall[k][0])
+            d.u_wall[k][1] = float(case.u_wall[k][1])
+        d.precision = precision
+        d.rho0 = float(case.rho0)
+        d.taylor_quad = taylor_quad
+        if stream is None:
+            try:
+                import torch
+                if torch.cuda.is_available():
+                    stream = torch.cuda.current_stream().cuda_stream
+            except Exception:
+                stream = None
+        d.stream = c_void_p(stream) if stream else None
+        d.flags = ALLOW_MOMENT_DEFECT if allow_defect else 0
+        if tile:
+            d.tile_x, d.tile_y = tile
+        self.desc = d
+        h = c_void_p()
+        check(lib().dugks_create(byref(d), byref(h)), "dugks_create")
+        self.h = h
+        self.precision = precision
+
+    # -- lifetime ------------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dugks_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(256)
+        check(lib().dugks_describe(self.h, buf, 256), "dugks_describe")
+        return buf.value.decode()
+
+    # -- state ---------------------------------------------------------------
+    def set_state(self, f):
+        p, mem, keep = _ptr_mem(f)
+        check(lib().dugks_set_state(self.h, p, mem), "dugks_set_state")
+
+    def init_equilibrium(self, rho, ux, uy):
+        ps = [_ptr_mem(a) for a in (rho, ux, uy)]
+        mems = {m for _, m, _ in ps}
+        if len(mems) != 1:
+            raise ValueError("rho, ux, uy must all live in the same memory")
+        check(lib().dugks_init_equilibrium(self.h, ps[0][0], ps[1][0], ps[2][0], mems.pop()),
+              "dugks_init_equilibrium")
+
+    def step(self, n: int = 1):
+        check(lib().dugks_step(self.h, int(n)), "dugks_step")
+
+    def sync(self):
+        check(lib().dugks_sync(self.h), "dugks_sync")
+
+    def set_tau(self, tau):
+        p, mem, keep = _ptr_mem(tau)
+        check(lib().dugks_set_tau(self.h, p, mem), "dugks_set_tau")
+
+    def moments(self, out=None):
+        """(rho, ux, uy) as numpy (ny, nx) arrays, or into given device tensors."""
+        if out is not None:
+            ps = [_ptr_mem(a) for a in out]
+            check(lib().dugks_moments(self.h, ps[0][0], ps[1][0], ps[2][0], ps[0][1]), "dugks_moments")
+            return out
+        r = np.empty(self.ncell)
+        u = np.empty(self.ncell)
+        v = np.empty(self.ncell)
+        check(lib().dugks_moments(self.h, c_void_p(r.ctypes.data), c_void_p(u.ctypes.data),
+                                  c_void_p(v.ctypes.data), MEM_HOST), "dugks_moments")
+        s = (self.ny, self.nx)
+        return r.reshape(s), u.reshape(s), v.reshape(s)
+
+    def _dist(self, fn, out):
+        if out is not None:
+            p, mem, keep = _ptr_mem(out)
+            check(fn(self.h, p, mem), fn.__name__)
+            return out
+        f = np.empty(self.nq * self.ncell)
+        check(fn(self.h, c_void_p(f.ctypes.data), MEM_HOST), fn.__name__)
+        return f.reshape(self.nq, self.ny, self.nx)
+
+    def get_state(self, out=None):
+        return self._dist(lib().dugks_get_state, out)
+
+    def get_fhat(self, out=None):
+        return self._dist(lib().dugks_get_fhat, out)
+
+    # -- timing --------------------------------------------------------------
+    def prof_begin(self, max_launches: int):
+        check(lib().dugks_prof_begin(self.h, int(max_launches)), "dugks_prof_begin")
+
+    def prof_query(self, kernel: int):
+        ms = c_double()
+        cnt = c_int()
+        check(lib().dugks_prof_query(self.h, int(kernel), byref(ms), byref(cnt)), "dugks_prof_query")
+        return ms.value, cnt.value
+
+    def prof_end(self):
+        check(lib().dugks_prof_end(self.h), "dugks_prof_end")

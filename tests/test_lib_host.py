@@ -1,0 +1,80 @@
+"""Host-side checks of the C-ABI library: it loads without a GPU, exports
+every symbol include/dugks.h declares, and rejects invalid descriptors before
+touching the device."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1709_05458_amd import cases as C
+from paper_1709_05458_amd import dugks
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "dugks.h")
+
+
+def declared_functions():
+    src = open(HDR).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dugks_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    L = dugks.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_strerror_covers_codes():
+    L = dugks.lib()
+    for code in range(0, -8, -1):
+        assert L.dugks_strerror(code) not in (b"", b"unknown error")
+    assert L.dugks_strerror(-99) == b"unknown error"
+
+
+def _expect(code, case, **kw):
+    with pytest.raises(dugks.DugksError) as e:
+        dugks.Solver(case, **kw)
+    assert e.value.code == code, str(e.value)
+
+
+def test_descriptor_validation_on_the_host():
+    case = C.tgv_case(16)
+    bad = C.tgv_case(16)
+    bad.tau[:] = bad.dt / 12.5           # beyond the dt/tau <= 12 bound of the paper
+    _expect(-2, bad)
+    bad = C.tgv_case(16)
+    bad.tau[3, 4] = bad.dt / 13.0        # one cell of a tau field
+    _expect(-2, bad)
+    bad = C.tgv_case(16)
+    bad.dt = 2.0 * bad.grid.dmin / bad.vs.cmax   # CFL 2
+    _expect(-1, bad)
+    bad = C.tgv_case(16)
+    bad.grid = C.uniform_grid(2, 16)     # too few cells
+    _expect(-1, bad)
+    bad = C.tgv_case(16)
+    bad.bc = (C.BC_PERIODIC, C.BC_BOUNCE_BACK, C.BC_PERIODIC, C.BC_PERIODIC)
+    _expect(-1, bad)
+    # weights that are not moment-exact are refused unless allowed
+    nc = C.cavity_case(16, C.newton_cotes(12, 0.5), wall=C.BC_DIFFUSE, tau=0.1)
+    _expect(-3, nc)
+    # bounce-back needs mirror velocities of equal weight
+    vs = C.d2q9(1 / 3)
+    vs.w = vs.w.copy()
+    vs.w[0], vs.w[8] = vs.w[0] * 1.1, vs.w[8] * 0.9
+    bb = C.cavity_case(16, vs, tau=0.1)
+    _expect(-1, bb)
+    # FP32-delta storage needs a reference density
+    c2 = C.tgv_case(16)
+    c2.rho0 = 0.0
+    _expect(-1, c2, precision=dugks.FP32_DELTA)
+    assert case is not None
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(dugks, "_lib", None)
+    monkeypatch.setattr(dugks, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(ImportError):
+        dugks.lib()
