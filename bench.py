@@ -36,7 +36,22 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", default="", help="tile as TXxTY")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    """A plain device-to-device copy of known size, for scaling the HBM byte
+    counters of a profiler against a kernel whose traffic is known."""
+    import torch
+    n = mib * 1024 * 1024
+    src = torch.ones(n, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "launches": 3}))
 
 
 def make_case(n, lattice):
@@ -102,6 +117,9 @@ def main():
     import torch
     from paper_1709_05458_amd import dugks
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
     case = make_case(args.n, args.lattice)
     Q = case.vs.nq

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -356,7 +357,6 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     p.kappa = d->taylor_quad > 0 ? d->taylor_quad : 1.0;
     p.tau0 = d->tau0;
     p.tau_field = d->tau != nullptr;
-    p.literal_fbp = 0;
     for (int k = 0; k < 4; k++) {
         p.bc[k] = d->bc[k];
         p.uw[k][0] = d->u_wall[k][0];
@@ -372,10 +372,33 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
         return fail(DUGKS_ENOTSUP, "velocity set is not D2Q9 or D2Q37 in the library's order");
     }
     p.clat = c;
+    p.nxcd = 8;   // MI355X: 8 XCDs
+    if (const char *e = getenv("DUGKS_NXCD")) p.nxcd = std::max(1, atoi(e));   // tuning knob
+    p.iRT = 1.0 / d->RT;
+    {
+        // coefficients of a uniform tau (used when no tau field is given)
+        const double t = d->tau0, dt = d->dt, h1 = dt / 6.0, h2 = 5.0 * dt / 12.0;
+        UniformCoef &u = p.uc;
+        u.cc[0] = (12.0 * t - dt) / (12.0 * t + 3.0 * dt);
+        u.ce[0] = 4.0 * dt / (12.0 * t + 3.0 * dt);
+        u.cc[1] = (24.0 * t - 5.0 * dt) / (24.0 * t + 4.0 * dt);
+        u.ce[1] = 9.0 * dt / (24.0 * t + 4.0 * dt);
+        u.c1 = u.cc[0];
+        u.e1 = u.ce[0];
+        const double kw = 6.0 * dt / (6.0 * t + dt);
+        u.a_f = (4.0 - 6.0 * u.c1) / 7.0;
+        u.a_En = -6.0 / 7.0 * u.e1;
+        u.a_G = 9.0 / 7.0 - 0.75 * kw;
+        u.a_Ep = 0.75 * kw;
+        u.alpha[0] = 2.0 * t / (2.0 * t + h1);
+        u.beta[0] = h1 / (2.0 * t + h1);
+        u.alpha[1] = 2.0 * t / (2.0 * t + h2);
+        u.beta[1] = h2 / (2.0 * t + h2);
+    }
 
     // tile
-    const int lx = d->tile_x > 0 ? d->tile_x : 32;
-    const int ly = d->tile_y > 0 ? d->tile_y : (h->lat == 37 && !h->delta ? 4 : 8);
+    const int lx = d->tile_x > 0 ? d->tile_x : (h->lat == 37 && !h->delta ? 16 : 32);
+    const int ly = d->tile_y > 0 ? d->tile_y : (h->lat == 37 && !h->delta ? 16 : 8);
     if (lx * ly > 512 || lx * ly < 64 || lx < 2 || ly < 2) {
         delete h;
         return fail(DUGKS_EINVAL, "tile must hold 64..512 cells");
@@ -412,6 +435,17 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     UP(ixd, p.g.inv_dx) UP(iyd, p.g.inv_dy)
     std::vector<double> vxi(xi, xi + nq), veta(eta, eta + nq), vw(d->w, d->w + nq);
     UP(vxi, p.xi) UP(veta, p.eta) UP(vw, p.w) UP(opp, p.opp)
+    {
+        // per-velocity moment weights in lattice units (e = xi / clat)
+        std::vector<double> wm(3 * (size_t)nq);
+        for (int q = 0; q < nq; q++) {
+            const double w0 = h->delta ? d->w[q] : 1.0;
+            wm[3 * q] = w0;
+            wm[3 * q + 1] = w0 * std::round(xi[q] / c);
+            wm[3 * q + 2] = w0 * std::round(eta[q] / c);
+        }
+        UP(wm, p.wmom)
+    }
     if (d->tau) {
         std::vector<double> vt(d->tau, d->tau + ncell);
         UP(vt, p.tau)

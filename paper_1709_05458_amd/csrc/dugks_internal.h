@@ -17,6 +17,14 @@ struct Geometry {
     const double *inv_dx, *inv_dy;      // [nx], [ny] 1 / cell width
 };
 
+// tau-dependent coefficients precomputed on the host when tau is uniform
+struct UniformCoef {
+    double cc[2], ce[2];        // pre-reconstruction transform of stage A / C
+    double c1, e1;              // fbar^{+,dt/6} = c1 fhat + e1 E
+    double a_f, a_En, a_G, a_Ep;   // stage C own-cell combination
+    double alpha[2], beta[2];   // interface recovery of stage A / C
+};
+
 // Everything a sweep kernel needs; passed by value as a kernel argument.
 struct SweepParams {
     int nx, ny;
@@ -35,10 +43,12 @@ struct SweepParams {
     const double *tau;       // [cell] or nullptr
     double tau0;
     int tau_field;
-    int literal_fbp;
+    UniformCoef uc;
+    double iRT;              // 1 / RT
     Geometry g;
     // velocity set (device)
     const double *xi, *eta, *w;
+    const double *wmom;      // [nq][3]: moment weights (w, w ex, w ey) in lattice units
     const int *opp;
     // walls
     int bc[4];
@@ -49,6 +59,7 @@ struct SweepParams {
     double ds_m[4][3];       // sum over leaving q of (1, xi, eta) w_q P_q(u_w)
     double ds_w[4][3];       // sum over leaving q of (1, xi, eta) w_q
     int tile_x, tile_y;
+    int nxcd;                // XCDs that workgroups are dealt to round-robin
 };
 
 // Kernel classes for event timing.

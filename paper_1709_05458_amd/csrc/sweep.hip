@@ -94,9 +94,9 @@ struct EPoly {
 };
 
 __device__ __forceinline__ EPoly epoly(double rho, double drho, double mx, double my,
-                                       double RT, double clat, bool delta)
+                                       double iRT_in, double clat, bool delta)
 {
-    const double ir = 1.0 / rho, iRT = 1.0 / RT;
+    const double ir = 1.0 / rho, iRT = iRT_in;
     const double ux = mx * ir, uy = my * ir;
     const double uu = ux * ux + uy * uy;
     EPoly e;
@@ -131,6 +131,28 @@ struct EPolyS {
         if (EX) v = fmaS((S)(EX * EX), c2xx, v);
         if (EX && EY) v = fmaS((S)(EX * EY), c2xy, v);
         if (EY) v = fmaS((S)(EY * EY), c2yy, v);
+        return v;
+    }
+};
+
+// sum over the monomials e_x^a e_y^b (1 <= a + b <= 3) of the flux's
+// equilibrium part; evaluated with compile-time integer e.
+template <class S>
+struct Cubic {
+    S x, y, xx, xy, yy, xxx, xxy, xyy, yyy;
+    template <int EX, int EY>
+    __device__ __forceinline__ S eval() const
+    {
+        S v = (S)0;
+        if (EX) v = fmaS((S)EX, x, v);
+        if (EY) v = fmaS((S)EY, y, v);
+        if (EX) v = fmaS((S)(EX * EX), xx, v);
+        if (EX && EY) v = fmaS((S)(EX * EY), xy, v);
+        if (EY) v = fmaS((S)(EY * EY), yy, v);
+        if (EX) v = fmaS((S)(EX * EX * EX), xxx, v);
+        if (EX && EY) v = fmaS((S)(EX * EX * EY), xxy, v);
+        if (EX && EY) v = fmaS((S)(EX * EY * EY), xyy, v);
+        if (EY) v = fmaS((S)(EY * EY * EY), yyy, v);
         return v;
     }
 };
@@ -206,14 +228,24 @@ struct ThreadState {
     S cx, cy;                     // -1/dx, -1/dy of the own cell
 };
 
+// Interface moment sums in double.  FP32-delta: sum w_q (1, ex, ey) x_q with
+// the products w_q ex, w_q ey read from a per-velocity table (scalar loads),
+// so that each term is one conversion and one to three FMAs.
 template <class Lat, class S, bool DELTA, int q>
-__device__ __forceinline__ void accumulate(ThreadState<Lat, S, DELTA> &t, int face, S v, double wq)
+__device__ __forceinline__ void accumulate(ThreadState<Lat, S, DELTA> &t, int face, S v,
+                                           const double *__restrict__ wm)
 {
     constexpr int EX = Lat::ex(q), EY = Lat::ey(q);
-    const double d = DELTA ? wq * (double)v : (double)v;
-    t.mr[face] += d;
-    if (EX) t.mx[face] = __builtin_fma((double)EX, d, t.mx[face]);
-    if (EY) t.my[face] = __builtin_fma((double)EY, d, t.my[face]);
+    const double d = (double)v;
+    if (DELTA) {
+        t.mr[face] = __builtin_fma(wm[3 * q], d, t.mr[face]);
+        if (EX) t.mx[face] = __builtin_fma(wm[3 * q + 1], d, t.mx[face]);
+        if (EY) t.my[face] = __builtin_fma(wm[3 * q + 2], d, t.my[face]);
+    } else {
+        t.mr[face] += d;
+        if (EX) t.mx[face] = __builtin_fma((double)EX, d, t.mx[face]);
+        if (EY) t.my[face] = __builtin_fma((double)EY, d, t.my[face]);
+    }
 }
 
 // Fast path: uniform grid, tile away from walls.  coef[q*24 + 0..11] are the
@@ -224,7 +256,7 @@ __device__ __forceinline__ void accumulate(ThreadState<Lat, S, DELTA> &t, int fa
 template <class Lat, class S, bool DELTA, int q>
 __device__ __forceinline__ void faces_fast(ThreadState<Lat, S, DELTA> &t, const S *lds, int plane,
                                            int HX, int base, const S *__restrict__ coef,
-                                           double wq, S xq_s, S yq_s)
+                                           const double *__restrict__ wm, S xq_s, S yq_s)
 {
     constexpr int EX = Lat::ex(q), EY = Lat::ey(q);
     const S *P = lds + q * plane + base;
@@ -250,10 +282,10 @@ __device__ __forceinline__ void faces_fast(ThreadState<Lat, S, DELTA> &t, const 
             vn = fmaS(c, P[(k - 1) * HX + (a - 1)], vn);
         }
     }
-    accumulate<Lat, S, DELTA, q>(t, 0, vw, wq);
-    accumulate<Lat, S, DELTA, q>(t, 1, ve, wq);
-    accumulate<Lat, S, DELTA, q>(t, 2, vs, wq);
-    accumulate<Lat, S, DELTA, q>(t, 3, vn, wq);
+    accumulate<Lat, S, DELTA, q>(t, 0, vw, wm);
+    accumulate<Lat, S, DELTA, q>(t, 1, ve, wm);
+    accumulate<Lat, S, DELTA, q>(t, 2, vs, wm);
+    accumulate<Lat, S, DELTA, q>(t, 3, vn, wm);
     S l = 0;
     if (EX) l = fmaS(xq_s * t.cx, t.ae * ve - t.aw * vw, l);
     if (EY) l = fmaS(yq_s * t.cy, t.an * vn - t.as_ * vs, l);
@@ -270,7 +302,7 @@ template <class Lat, class S, bool DELTA, int q>
 __device__ __forceinline__ void faces_general(ThreadState<Lat, S, DELTA> &t, const SweepParams &p,
                                               const S *lds, int plane, int HX, int hxo, int hyo,
                                               int i, int j, double h, double rho_own, double wq,
-                                              S xq_s, S yq_s)
+                                              const double *__restrict__ wm, S xq_s, S yq_s)
 {
     constexpr int EX = Lat::ex(q), EY = Lat::ey(q);
     constexpr int O = Lat::opp(q);
@@ -374,10 +406,10 @@ __device__ __forceinline__ void faces_general(ThreadState<Lat, S, DELTA> &t, con
         v[2 + s] = val;
     }
     const S vw = (S)v[0], ve = (S)v[1], vs = (S)v[2], vn = (S)v[3];
-    if (!defer[0]) accumulate<Lat, S, DELTA, q>(t, 0, vw, wq);
-    if (!defer[1]) accumulate<Lat, S, DELTA, q>(t, 1, ve, wq);
-    if (!defer[2]) accumulate<Lat, S, DELTA, q>(t, 2, vs, wq);
-    if (!defer[3]) accumulate<Lat, S, DELTA, q>(t, 3, vn, wq);
+    if (!defer[0]) accumulate<Lat, S, DELTA, q>(t, 0, vw, wm);
+    if (!defer[1]) accumulate<Lat, S, DELTA, q>(t, 1, ve, wm);
+    if (!defer[2]) accumulate<Lat, S, DELTA, q>(t, 2, vs, wm);
+    if (!defer[3]) accumulate<Lat, S, DELTA, q>(t, 3, vn, wm);
     S l = 0;
     if (EX) l = fmaS(xq_s * t.cx, t.ae * ve - t.aw * vw, l);
     if (EY) l = fmaS(yq_s * t.cy, t.an * vn - t.as_ * vs, l);
@@ -392,13 +424,20 @@ __device__ __forceinline__ void load_q(const S *__restrict__ X, long long n, lon
 }
 
 template <class Lat, class S, bool DELTA, int q>
-__device__ __forceinline__ void moment_q(const S *v, double wq, double &a0, double &ax, double &ay)
+__device__ __forceinline__ void moment_q(const S *v, const double *__restrict__ wm, double &a0,
+                                         double &ax, double &ay)
 {
     constexpr int EX = Lat::ex(q), EY = Lat::ey(q);
-    const double d = DELTA ? wq * (double)v[q] : (double)v[q];
-    a0 += d;
-    if (EX) ax = __builtin_fma((double)EX, d, ax);
-    if (EY) ay = __builtin_fma((double)EY, d, ay);
+    const double d = (double)v[q];
+    if (DELTA) {
+        a0 = __builtin_fma(wm[3 * q], d, a0);
+        if (EX) ax = __builtin_fma(wm[3 * q + 1], d, ax);
+        if (EY) ay = __builtin_fma(wm[3 * q + 2], d, ay);
+    } else {
+        a0 += d;
+        if (EX) ax = __builtin_fma((double)EX, d, ax);
+        if (EY) ay = __builtin_fma((double)EY, d, ay);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -407,6 +446,23 @@ __device__ __forceinline__ void moment_q(const S *v, double wq, double &a0, doub
 // tiles (walls, one-sided stencils, non-uniform spacing).  Each instance
 // returns at once on the tiles of the other kind.
 // ---------------------------------------------------------------------------
+// Workgroups are dealt to the XCDs round-robin (block b runs on XCD b % nxcd).
+// Give every XCD a contiguous range of row-major tiles so that neighbouring
+// tiles, which read each other's halo, share that XCD's L2.
+__device__ __forceinline__ void tile_of_block(const SweepParams &p, int &tx, int &ty)
+{
+    const int gx = (p.nx + p.tile_x - 1) / p.tile_x;
+    const int gy = (p.ny + p.tile_y - 1) / p.tile_y;
+    const int nb = gx * gy;
+    const int b = blockIdx.x;
+    const int nx8 = p.nxcd;
+    const int per = nb / nx8, rem = nb % nx8;
+    const int x = b % nx8, slot = b / nx8;
+    const int t = x * per + (x < rem ? x : rem) + slot;
+    tx = t % gx;
+    ty = t / gx;
+}
+
 __device__ __forceinline__ bool tile_is_fast(const SweepParams &p, int i0, int j0, int TX, int TY)
 {
     return p.uniform && (p.perx || (i0 >= 2 && i0 + TX <= p.nx - 2)) &&
@@ -424,7 +480,9 @@ sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
     S *lds = reinterpret_cast<S *>(smem_raw);
 
     const int TX = p.tile_x, TY = p.tile_y;
-    const int i0 = blockIdx.x * TX, j0 = blockIdx.y * TY;
+    int tx, ty;
+    tile_of_block(p, tx, ty);
+    const int i0 = tx * TX, j0 = ty * TY;
     if (tile_is_fast(p, i0, j0, TX, TY) == GENERAL) return;   // whole block: no barrier skipped
 
     const int HX = TX + 4;
@@ -437,10 +495,11 @@ sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
     const long long n = p.ncell;
     const double dt = p.dt, RT = p.RT, cl = p.clat;
     const double *__restrict__ W = p.w;
+    const double *__restrict__ WM = p.wmom;
     const long long ocell = (long long)j * p.nx + i;
     const double tau_o = (p.tau_field && valid) ? p.tau[ocell] : p.tau0;
-    const double c1 = (12.0 * tau_o - dt) / (12.0 * tau_o + 3.0 * dt);
-    const double e1 = 4.0 * dt / (12.0 * tau_o + 3.0 * dt);
+    const double c1 = p.tau_field ? (12.0 * tau_o - dt) / (12.0 * tau_o + 3.0 * dt) : p.uc.c1;
+    const double e1 = p.tau_field ? 4.0 * dt / (12.0 * tau_o + 3.0 * dt) : p.uc.e1;
 
     ThreadState<Lat, S, DELTA> t;
     double o_rho = 1.0;
@@ -460,7 +519,7 @@ sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
         if (in) {
             [&]<int... qs>(std::integer_sequence<int, qs...>) {
                 (load_q<Lat, S, DELTA, qs>(X, n, cell, v), ...);
-                (moment_q<Lat, S, DELTA, qs>(v, W[qs], a0, ax, ay), ...);
+                (moment_q<Lat, S, DELTA, qs>(v, WM, a0, ax, ay), ...);
             }(Seq{});
         } else {
 #pragma unroll
@@ -472,17 +531,17 @@ sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
         if (!in) { rho = 1.0; drho = DELTA ? 0.0 : 1.0; mx = my = 0.0; }
         const double tau = (p.tau_field && in) ? p.tau[cell] : p.tau0;
         double cc, ce;
-        if (STAGE == 0) {   // eq. f_bar_1_6
+        if (!p.tau_field) {
+            cc = p.uc.cc[STAGE];
+            ce = p.uc.ce[STAGE];
+        } else if (STAGE == 0) {   // eq. f_bar_1_6
             cc = (12.0 * tau - dt) / (12.0 * tau + 3.0 * dt);
             ce = 4.0 * dt / (12.0 * tau + 3.0 * dt);
-        } else if (p.literal_fbp) {   // eq. fbp_5_12 as printed
-            cc = (24.0 * tau - 5.0 * dt) / (24.0 * tau + 10.0 * dt);
-            ce = 15.0 * dt / (24.0 * tau + 10.0 * dt);
         } else {   // eq. fbp_5_12 with the coefficients that map tilde f onto fbar^{+,5dt/12}
             cc = (24.0 * tau - 5.0 * dt) / (24.0 * tau + 4.0 * dt);
             ce = 9.0 * dt / (24.0 * tau + 4.0 * dt);
         }
-        const EPoly ep_cell = epoly(rho, drho, mx, my, RT, cl, DELTA);
+        const EPoly ep_cell = epoly(rho, drho, mx, my, p.iRT, cl, DELTA);
         EPolyS<S> e;
         e.set(ep_cell, ce);
         const S ccs = (S)cc;
@@ -514,17 +573,20 @@ sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
                 double b0 = 0, bx = 0, by = 0;
                 [&]<int... qs>(std::integer_sequence<int, qs...>) {
                     (load_q<Lat, S, DELTA, qs>(F, n, ocell, fh), ...);
-                    (moment_q<Lat, S, DELTA, qs>(fh, W[qs], b0, bx, by), ...);
+                    (moment_q<Lat, S, DELTA, qs>(fh, WM, b0, bx, by), ...);
                 }(Seq{});
                 double rn, drn, mxn, myn;
                 phys_moments(p, DELTA, b0, bx, by, rn, drn, mxn, myn);
-                const double kw = 6.0 * dt / (6.0 * tau_o + dt);
-                const double a_f = (4.0 - 6.0 * c1) / 7.0;
-                const double a_En = -6.0 / 7.0 * e1;
-                const double a_G = 9.0 / 7.0 - 0.75 * kw;
-                const double a_Ep = 0.75 * kw;
+                double a_f = p.uc.a_f, a_En = p.uc.a_En, a_G = p.uc.a_G, a_Ep = p.uc.a_Ep;
+                if (p.tau_field) {
+                    const double kw = 6.0 * dt / (6.0 * tau_o + dt);
+                    a_f = (4.0 - 6.0 * c1) / 7.0;
+                    a_En = -6.0 / 7.0 * e1;
+                    a_G = 9.0 / 7.0 - 0.75 * kw;
+                    a_Ep = 0.75 * kw;
+                }
                 EPolyS<S> en, ep;
-                en.set(epoly(rn, drn, mxn, myn, RT, cl, DELTA), a_En);
+                en.set(epoly(rn, drn, mxn, myn, p.iRT, cl, DELTA), a_En);
                 ep.set(ep_cell, a_Ep);
                 const S sf = (S)a_f, sg = (S)a_G;
                 [&]<int... qs>(std::integer_sequence<int, qs...>) {
@@ -562,8 +624,13 @@ sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
     double alpha[4], beta[4];
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        alpha[k] = 2.0 * tb[k] / (2.0 * tb[k] + h);
-        beta[k] = h / (2.0 * tb[k] + h);
+        if (p.tau_field) {
+            alpha[k] = 2.0 * tb[k] / (2.0 * tb[k] + h);
+            beta[k] = h / (2.0 * tb[k] + h);
+        } else {
+            alpha[k] = p.uc.alpha[STAGE];
+            beta[k] = p.uc.beta[STAGE];
+        }
     }
     t.aw = (S)alpha[0]; t.ae = (S)alpha[1]; t.as_ = (S)alpha[2]; t.an = (S)alpha[3];
     const double idx = p.uniform ? p.inv_dx : p.g.inv_dx[i];
@@ -578,13 +645,13 @@ sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
     if (!GENERAL) {
         const int base = (ly + 2) * HX + (lx + 2);
         [&]<int... qs>(std::integer_sequence<int, qs...>) {
-            (faces_fast<Lat, S, DELTA, qs>(t, lds, plane, HX, base, coef, W[qs],
+            (faces_fast<Lat, S, DELTA, qs>(t, lds, plane, HX, base, coef, WM,
                                            cls * (S)Lat::ex(qs), cls * (S)Lat::ey(qs)), ...);
         }(Seq{});
     } else {
         [&]<int... qs>(std::integer_sequence<int, qs...>) {
             (faces_general<Lat, S, DELTA, qs>(t, p, lds, plane, HX, lx + 2, ly + 2, i, j, h, o_rho,
-                                              W[qs], cls * (S)Lat::ex(qs), cls * (S)Lat::ey(qs)),
+                                              W[qs], WM, cls * (S)Lat::ex(qs), cls * (S)Lat::ey(qs)),
              ...);
         }(Seq{});
     }
@@ -620,29 +687,31 @@ sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
         // reuse slot: store my in t.my
         t.my[k] = my;
     }
-    // equilibrium part beta_b E_b of the recovered interface values, as
-    // east-minus-west and north-minus-south polynomials
-    EPolyS<S> dEx, dEy;
+    // Equilibrium part beta_b E_b of the recovered interface values enters
+    // L_q as -(xi_x/dx)(beta_e E_e - beta_w E_w) - (xi_y/dy)(beta_n E_n - beta_s E_s);
+    // with xi = clat e this is one cubic polynomial in the integer vector e.
+    Cubic<S> cub;
     {
-        const EPoly ew = epoly(M[0][0], M[0][1], M[0][2], t.my[0], RT, cl, DELTA);
-        const EPoly ee = epoly(M[1][0], M[1][1], M[1][2], t.my[1], RT, cl, DELTA);
-        const EPoly es = epoly(M[2][0], M[2][1], M[2][2], t.my[2], RT, cl, DELTA);
-        const EPoly en = epoly(M[3][0], M[3][1], M[3][2], t.my[3], RT, cl, DELTA);
-        EPoly dx, dy;
-        dx.c0 = beta[1] * ee.c0 - beta[0] * ew.c0;
-        dx.c1x = beta[1] * ee.c1x - beta[0] * ew.c1x;
-        dx.c1y = beta[1] * ee.c1y - beta[0] * ew.c1y;
-        dx.c2xx = beta[1] * ee.c2xx - beta[0] * ew.c2xx;
-        dx.c2xy = beta[1] * ee.c2xy - beta[0] * ew.c2xy;
-        dx.c2yy = beta[1] * ee.c2yy - beta[0] * ew.c2yy;
-        dy.c0 = beta[3] * en.c0 - beta[2] * es.c0;
-        dy.c1x = beta[3] * en.c1x - beta[2] * es.c1x;
-        dy.c1y = beta[3] * en.c1y - beta[2] * es.c1y;
-        dy.c2xx = beta[3] * en.c2xx - beta[2] * es.c2xx;
-        dy.c2xy = beta[3] * en.c2xy - beta[2] * es.c2xy;
-        dy.c2yy = beta[3] * en.c2yy - beta[2] * es.c2yy;
-        dEx.set(dx, 1.0);
-        dEy.set(dy, 1.0);
+        const EPoly ew = epoly(M[0][0], M[0][1], M[0][2], t.my[0], p.iRT, cl, DELTA);
+        const EPoly ee = epoly(M[1][0], M[1][1], M[1][2], t.my[1], p.iRT, cl, DELTA);
+        const EPoly es = epoly(M[2][0], M[2][1], M[2][2], t.my[2], p.iRT, cl, DELTA);
+        const EPoly en = epoly(M[3][0], M[3][1], M[3][2], t.my[3], p.iRT, cl, DELTA);
+        const double kx = -idx * cl, ky = -idy * cl;
+        const double a0 = beta[1] * ee.c0 - beta[0] * ew.c0, a1 = beta[1] * ee.c1x - beta[0] * ew.c1x,
+                     a2 = beta[1] * ee.c1y - beta[0] * ew.c1y, a3 = beta[1] * ee.c2xx - beta[0] * ew.c2xx,
+                     a4 = beta[1] * ee.c2xy - beta[0] * ew.c2xy, a5 = beta[1] * ee.c2yy - beta[0] * ew.c2yy;
+        const double b0 = beta[3] * en.c0 - beta[2] * es.c0, b1 = beta[3] * en.c1x - beta[2] * es.c1x,
+                     b2 = beta[3] * en.c1y - beta[2] * es.c1y, b3 = beta[3] * en.c2xx - beta[2] * es.c2xx,
+                     b4 = beta[3] * en.c2xy - beta[2] * es.c2xy, b5 = beta[3] * en.c2yy - beta[2] * es.c2yy;
+        cub.x = (S)(kx * a0);
+        cub.y = (S)(ky * b0);
+        cub.xx = (S)(kx * a1);
+        cub.xy = (S)(kx * a2 + ky * b1);
+        cub.yy = (S)(ky * b2);
+        cub.xxx = (S)(kx * a3);
+        cub.xxy = (S)(kx * a4 + ky * b3);
+        cub.xyy = (S)(kx * a5 + ky * b4);
+        cub.yyy = (S)(ky * b5);
     }
     const bool anyds = GENERAL && (dsf[0] || dsf[1] || dsf[2] || dsf[3]);
     const S r0s = (S)(DELTA ? p.rho0 : 0.0);
@@ -655,9 +724,8 @@ sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
              constexpr int EX = Lat::ex(q), EY = Lat::ey(q);
              const S xq = cls * (S)EX, yq = cls * (S)EY;
              S L = t.La[q];
-             const S sq = DELTA ? (S)1 : (S)W[q];
-             if (EX) L = fmaS(xq * t.cx, sq * dEx.template eval<EX, EY>(), L);
-             if (EY) L = fmaS(yq * t.cy, sq * dEy.template eval<EX, EY>(), L);
+             if (DELTA) L += cub.template eval<EX, EY>();
+             else L = fmaS((S)W[q], cub.template eval<EX, EY>(), L);
              if (GENERAL && anyds) {
                  // leaving velocities of diffuse walls: fbar = E(rho_w, u_w)
                  if (EX > 0 && dsf[0]) L = fmaS(-(xq * t.cx) * t.aw, (S)rw[0] * (S)p.wall_E[0 * nq + q] - r0s, L);
@@ -679,7 +747,7 @@ template <class Lat, class S, bool DELTA, int STAGE>
 static hipError_t launch_t(const SweepParams &p, double h, const void *X, const void *F, void *out,
                            const void *coef, hipStream_t s)
 {
-    dim3 grid((p.nx + p.tile_x - 1) / p.tile_x, (p.ny + p.tile_y - 1) / p.tile_y);
+    dim3 grid(((p.nx + p.tile_x - 1) / p.tile_x) * ((p.ny + p.tile_y - 1) / p.tile_y));
     dim3 block(p.tile_x * p.tile_y);
     size_t smem = sizeof(S) * Lat::Q * (size_t)(p.tile_x + 4) * (p.tile_y + 4);
     // tiles of the fast kind exist unless the grid is non-uniform; tiles of the
