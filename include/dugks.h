@@ -65,7 +65,8 @@ enum dugks_precision {
 enum dugks_mem { DUGKS_MEM_HOST = 0, DUGKS_MEM_DEVICE = 1 };
 
 enum dugks_flags {
-    DUGKS_ALLOW_MOMENT_DEFECT = 1   /* accept weights that are not moment-exact (e.g. Newton-Cotes) */
+    DUGKS_ALLOW_MOMENT_DEFECT = 1,  /* accept weights that are not moment-exact (e.g. Newton-Cotes) */
+    DUGKS_FORCE_GENERIC = 2         /* use the any-size velocity-set kernels even for D2Q9 / D2Q37 */
 };
 
 /* Creation descriptor.  Pointers are host pointers, read only during
@@ -101,9 +102,14 @@ typedef struct {
  * Checks: nx, ny >= 3; faces increasing; periodic sides paired; dt > 0,
  * RT > 0, tau > 0; max dt/tau <= 12 (else DUGKS_EUNSTABLE); bounce-back needs
  * every velocity to have a mirror with the same weight (else EINVAL); weight
- * moments (else DUGKS_EMOMENT unless DUGKS_ALLOW_MOMENT_DEFECT).  On success
- * *out owns device buffers sized 3 * nq * nx * ny elements plus small tables;
- * the state is undefined until set_state or init_equilibrium. */
+ * moments (else DUGKS_EMOMENT unless DUGKS_ALLOW_MOMENT_DEFECT).
+ * Velocity sets equal to the library's D2Q9 or D2Q37 lattice (xi = c e_q in
+ * its order) run the lattice kernels; any other set (e.g. Newton-Cotes
+ * grids) runs the any-size kernels, which support periodic and diffuse
+ * boundaries (bounce-back: DUGKS_ENOTSUP).  On success *out owns device
+ * buffers of 3 * nq * nx * ny elements plus small tables (any-size kernels:
+ * also per-chunk interface and cell moment sums); the state is undefined
+ * until set_state or init_equilibrium. */
 int dugks_create(const dugks_desc *d, dugks_t **out);
 
 /* Release every resource of h.  h == NULL is a no-op. */

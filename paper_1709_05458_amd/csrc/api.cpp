@@ -27,6 +27,9 @@ struct dugks {
     void *coefA = nullptr, *coefC = nullptr;
     double h1 = 0, h2 = 0;
     int *d_bad = nullptr;
+    // any-size velocity sets
+    double *mom_state = nullptr, *mom_G = nullptr, *face_part = nullptr, *face_mom = nullptr,
+           *cell_part = nullptr;
     std::vector<void *> allocs;
     // timing
     std::vector<hipEvent_t> ev;   // pairs
@@ -365,11 +368,16 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
 
     // lattice
     double c = 0;
-    if (match_lattice(d->xi, nq, kD2Q9x, kD2Q9y, 9, c)) h->lat = 9;
-    else if (match_lattice(d->xi, nq, kD2Q37x, kD2Q37y, 37, c)) h->lat = 37;
+    const bool force_generic = d->flags & DUGKS_FORCE_GENERIC;
+    if (!force_generic && match_lattice(d->xi, nq, kD2Q9x, kD2Q9y, 9, c)) h->lat = 9;
+    else if (!force_generic && match_lattice(d->xi, nq, kD2Q37x, kD2Q37y, 37, c)) h->lat = 37;
     else {
-        delete h;
-        return fail(DUGKS_ENOTSUP, "velocity set is not D2Q9 or D2Q37 in the library's order");
+        h->lat = 0;
+        c = 1.0;
+        if (any_bb) {
+            delete h;
+            return fail(DUGKS_ENOTSUP, "bounce-back walls need the D2Q9 / D2Q37 lattice kernels");
+        }
     }
     p.clat = c;
     p.nxcd = 8;   // MI355X: 8 XCDs
@@ -397,21 +405,34 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     }
 
     // tile
-    const int lx = d->tile_x > 0 ? d->tile_x : (h->lat == 37 && !h->delta ? 16 : 32);
-    const int ly = d->tile_y > 0 ? d->tile_y : (h->lat == 37 && !h->delta ? 16 : 8);
-    if (lx * ly > 512 || lx * ly < 64 || lx < 2 || ly < 2) {
+    const int dlx = h->lat == 0 ? 16 : (h->lat == 37 && !h->delta ? 16 : 32);
+    const int dly = h->lat == 0 ? 16 : (h->lat == 37 && !h->delta ? 16 : 8);
+    const int lx = d->tile_x > 0 ? d->tile_x : dlx;
+    const int ly = d->tile_y > 0 ? d->tile_y : dly;
+    const int maxthr = h->lat == 0 ? 256 : 512;
+    if (lx * ly > maxthr || lx * ly < 64 || lx < 2 || ly < 2) {
         delete h;
-        return fail(DUGKS_EINVAL, "tile must hold 64..512 cells");
+        return fail(DUGKS_EINVAL, "tile must hold 64..512 cells (64..256 for any-size velocity sets)");
     }
     p.tile_x = lx;
     p.tile_y = ly;
-    const size_t smem = h->elem * nq * (size_t)(lx + 4) * (ly + 4);
+    if (h->lat == 0) {
+        // chunks: enough workgroups to fill the chip, at least 16 velocities each
+        const long long ntile = (long long)((d->nx + lx - 1) / lx) * ((d->ny + ly - 1) / ly);
+        int nch = (int)std::max(1LL, (2048 + ntile - 1) / ntile);
+        nch = std::min(nch, std::max(1, nq / 16));
+        p.lq_chunk = (nq + nch - 1) / nch;
+        p.lq_nchunk = (nq + p.lq_chunk - 1) / p.lq_chunk;
+        p.lq_qs = 8;
+    }
+    const size_t smem = h->lat == 0 ? lq_smem_bytes(p, h->delta)
+                                    : h->elem * nq * (size_t)(lx + 4) * (ly + 4);
     if (smem > 160 * 1024) {
         delete h;
         return fail(DUGKS_EINVAL, "tile too large for LDS");
     }
     {
-        hipError_t e = set_stage_smem(h->lat, h->delta, smem);
+        hipError_t e = h->lat == 0 ? set_lq_smem(h->delta, smem) : set_stage_smem(h->lat, h->delta, smem);
         if (e != hipSuccess) {
             delete h;
             return fail(DUGKS_EDEVICE, std::string("LDS size: ") + hipGetErrorString(e));
@@ -515,13 +536,33 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
         dugks_destroy(h);
         return rc;
     }
+    if (h->lat == 0) {
+        const size_t nface = (size_t)(d->nx + 1) * d->ny + (size_t)d->nx * (d->ny + 1);
+        void *a = nullptr, *b = nullptr, *fp = nullptr, *fm = nullptr, *cp = nullptr;
+        if ((rc = dalloc(h, &a, 32 * (size_t)ncell)) || (rc = dalloc(h, &b, 32 * (size_t)ncell)) ||
+            (rc = dalloc(h, &fp, 32 * nface * p.lq_nchunk)) || (rc = dalloc(h, &fm, 64 * nface)) ||
+            (rc = dalloc(h, &cp, 32 * (size_t)ncell * p.lq_nchunk))) {
+            dugks_destroy(h);
+            return rc;
+        }
+        h->mom_state = (double *)a;
+        h->mom_G = (double *)b;
+        h->face_part = (double *)fp;
+        h->face_mom = (double *)fm;
+        h->cell_part = (double *)cp;
+    }
     void *bad = nullptr;
     if ((rc = dalloc(h, &bad, sizeof(int)))) { dugks_destroy(h); return rc; }
     h->d_bad = (int *)bad;
     HIPCHECK(hipMemset(h->d_bad, 0, sizeof(int)));
     char buf[128];
-    snprintf(buf, sizeof buf, "small-Q D2Q%d %s tile %dx%d %s", h->lat, h->delta ? "fp32-delta" : "fp64",
-             lx, ly, unif ? "uniform" : "non-uniform");
+    if (h->lat)
+        snprintf(buf, sizeof buf, "lattice D2Q%d %s tile %dx%d %s", h->lat, h->delta ? "fp32-delta" : "fp64",
+                 lx, ly, unif ? "uniform" : "non-uniform");
+    else
+        snprintf(buf, sizeof buf, "any-size Q=%d %s tile %dx%d, %d chunks of %d velocities, %s", nq,
+                 h->delta ? "fp32-delta" : "fp64", lx, ly, p.lq_nchunk, p.lq_chunk,
+                 unif ? "uniform" : "non-uniform");
     h->variant = buf;
     *out = h;
     return DUGKS_OK;
@@ -562,6 +603,7 @@ int dugks_set_state(dugks_t *h, const double *f, int mem)
     int rc = stage_in(f, (size_t)h->p.nq * h->p.ncell, mem, s, h->stream);
     if (rc) return rc;
     HIPCHECK(launch_set_state(h->p, h->delta, s.dev, h->state[h->cur], h->stream));
+    if (h->lat == 0) HIPCHECK(launch_state_moments(h->p, h->delta, h->state[h->cur], h->mom_state, h->stream));
     HIPCHECK(hipStreamSynchronize(h->stream));
     return DUGKS_OK;
 }
@@ -577,6 +619,7 @@ int dugks_init_equilibrium(dugks_t *h, const double *rho, const double *ux, cons
         (rc = stage_in(uy, n, mem, c, h->stream)))
         return rc;
     HIPCHECK(launch_init_eq(h->p, h->delta, a.dev, b.dev, c.dev, h->state[h->cur], h->stream));
+    if (h->lat == 0) HIPCHECK(launch_state_moments(h->p, h->delta, h->state[h->cur], h->mom_state, h->stream));
     HIPCHECK(hipStreamSynchronize(h->stream));
     return DUGKS_OK;
 }
@@ -600,10 +643,24 @@ int dugks_step(dugks_t *h, int nsteps)
         void *X = h->state[h->cur], *Y = h->state[1 - h->cur];
         int rc;
         if ((rc = record(h, KC_STAGE_A, true))) return rc;
-        HIPCHECK(launch_stage(0, h->lat, h->delta, h->p, h->h1, X, nullptr, h->G, h->coefA, h->stream));
+        if (h->lat) {
+            HIPCHECK(launch_stage(0, h->lat, h->delta, h->p, h->h1, X, nullptr, h->G, h->coefA, h->stream));
+        } else {
+            LQStage a{X, nullptr, h->G, h->mom_state, nullptr, h->face_part, h->face_mom,
+                      h->cell_part, h->mom_G, h->h1, 0};
+            HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
+        }
         if ((rc = record(h, KC_STAGE_A, false))) return rc;
         if ((rc = record(h, KC_STAGE_C, true))) return rc;
-        HIPCHECK(launch_stage(1, h->lat, h->delta, h->p, h->h2, h->G, X, Y, h->coefC, h->stream));
+        if (h->lat) {
+            HIPCHECK(launch_stage(1, h->lat, h->delta, h->p, h->h2, h->G, X, Y, h->coefC, h->stream));
+        } else {
+            // the moments of fhat(t_n) are read by the update and overwritten by
+            // the cell reduction that follows it on the same stream
+            LQStage a{h->G, X, Y, h->mom_G, h->mom_state, h->face_part, h->face_mom,
+                      h->cell_part, h->mom_state, h->h2, 1};
+            HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
+        }
         if ((rc = record(h, KC_STAGE_C, false))) return rc;
         h->cur = 1 - h->cur;
     }

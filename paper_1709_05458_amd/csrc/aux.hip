@@ -95,6 +95,9 @@ __global__ void k_get_state(const SweepParams p, const S *__restrict__ x, double
     }
 }
 
+// f = E(rho, u), stored as fhat = f + dt/(4 tau) (f - E(moments of f)); the
+// second term vanishes for moment-exact weights but not for, e.g., Newton-Cotes
+// weights with a quadrature defect.
 template <class S, bool DELTA>
 __global__ void k_init_eq(const SweepParams p, const double *__restrict__ rho,
                           const double *__restrict__ ux, const double *__restrict__ uy,
@@ -104,15 +107,26 @@ __global__ void k_init_eq(const SweepParams p, const double *__restrict__ rho,
     if (cell >= p.ncell) return;
     const long long n = p.ncell;
     const double r = rho[cell], u = ux[cell], v = uy[cell];
+    double rf = 0, mfx = 0, mfy = 0;
     for (int q = 0; q < p.nq; q++) {
+        const double f = p.w[q] * r * eq_poly(p, q, u, v);
+        rf += f;
+        mfx += p.xi[q] * f;
+        mfy += p.eta[q] * f;
+    }
+    const double uf = mfx / rf, vf = mfy / rf;
+    const double tau = p.tau_field ? p.tau[cell] : p.tau0;
+    const double k = p.dt / (4.0 * tau);
+    for (int q = 0; q < p.nq; q++) {
+        const double P = eq_poly(p, q, u, v);
+        const double Pf = eq_poly(p, q, uf, vf);
         if (DELTA) {
-            // E_q / w_q - rho0 without forming rho * 1 - rho0 by cancellation
-            const double eu = p.xi[q] * u + p.eta[q] * v;
-            const double uu = u * u + v * v;
-            const double dev = eu / p.RT + eu * eu / (2.0 * p.RT * p.RT) - uu / (2.0 * p.RT);
-            x[q * n + cell] = (S)((r - p.rho0) + r * dev);
+            // fhat / w_q - rho0 without forming rho - rho0 by cancellation
+            const double dev = (r - p.rho0) + r * (P - 1.0);
+            x[q * n + cell] = (S)(dev + k * (r * P - rf * Pf));
         } else {
-            x[q * n + cell] = (S)(p.w[q] * r * eq_poly(p, q, u, v));
+            const double f = p.w[q] * r * P;
+            x[q * n + cell] = (S)(f + k * (f - p.w[q] * rf * Pf));
         }
     }
 }

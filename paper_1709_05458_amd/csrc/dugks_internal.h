@@ -60,6 +60,24 @@ struct SweepParams {
     double ds_w[4][3];       // sum over leaving q of (1, xi, eta) w_q
     int tile_x, tile_y;
     int nxcd;                // XCDs that workgroups are dealt to round-robin
+    // large velocity sets: q split into lq_nchunk chunks of lq_chunk velocities,
+    // streamed through LDS lq_qs planes at a time
+    int lq_chunk, lq_nchunk, lq_qs;
+};
+
+// Per-stage arguments of the large-velocity-set kernels.
+struct LQStage {
+    const void *X;          // stage input (fhat or tilde f), storage units
+    const void *F;          // stage C: fhat(t_n)
+    void *out;              // stage output
+    const double *momX;     // [cell][4] (rho, rho - rho0 or rho, rho ux, rho uy) of X
+    const double *momF;     // [cell][4] of F (stage C)
+    double *face_part;      // [chunk][face][4] partial interface sums
+    double *face_mom;       // [face][8] interface moments and diffuse-wall density
+    double *cell_part;      // [chunk][cell][4] partial cell moments of out
+    double *mom_out;        // [cell][4] cell moments of out
+    double h;               // characteristic step of the stage
+    int stage;              // 0: stage A, 1: stage C
 };
 
 // Kernel classes for event timing.
@@ -71,6 +89,13 @@ hipError_t launch_stage(int stage, int lat, bool delta, const SweepParams &p, do
                         const void *X, const void *F, void *out, const void *coef,
                         hipStream_t s);
 hipError_t set_stage_smem(int lat, bool delta, size_t bytes);
+
+// Large velocity sets (sweep_large.hip).  part < 0: all four kernels of the stage.
+hipError_t launch_lq_stage(bool delta, const SweepParams &p, const LQStage &a, hipStream_t s, int part);
+hipError_t set_lq_smem(bool delta, size_t bytes);
+size_t lq_smem_bytes(const SweepParams &p, bool delta);
+hipError_t launch_state_moments(const SweepParams &p, bool delta, const void *state, double *mom,
+                                hipStream_t s);
 
 // Auxiliary per-cell kernels (state conversions, moments); defined in aux.hip.
 hipError_t launch_set_state(const SweepParams &p, bool delta, const double *f, void *state,

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libdugks.so")
 FP64, FP32_DELTA = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 ALLOW_MOMENT_DEFECT = 1
+FORCE_GENERIC = 2
 K_STAGE_A, K_STAGE_C, K_AUX = 0, 1, 2
 
 STATUS = {0: "DUGKS_OK", -1: "DUGKS_EINVAL", -2: "DUGKS_EUNSTABLE", -3: "DUGKS_EMOMENT",
@@ -110,7 +111,7 @@ class Solver:
     """One T3S3-DUGKS solver instance (a dugks_t handle)."""
 
     def __init__(self, case, precision: int = FP64, taylor_quad: float = 1.0, stream=None,
-                 tile=None, allow_defect: bool = False, tau=None):
+                 tile=None, allow_defect: bool = False, tau=None, force_generic: bool = False):
         g, vs = case.grid, case.vs
         self.case = case
         self.nx, self.ny, self.nq = g.nx, g.ny, vs.nq
@@ -151,7 +152,7 @@ class Solver:
             except Exception:
                 stream = None
         d.stream = c_void_p(stream) if stream else None
-        d.flags = ALLOW_MOMENT_DEFECT if allow_defect else 0
+        d.flags = (ALLOW_MOMENT_DEFECT if allow_defect else 0) | (FORCE_GENERIC if force_generic else 0)
         if tile:
             d.tile_x, d.tile_y = tile
         self.desc = d

@@ -73,6 +73,22 @@ def _mk(name):
     if name == "cavity_bb_d2q37_48":
         c = C.cavity_case(48, C.d2q37(1.0 / 3.0), re=200.0)
         return _perturb(c, 10)
+    if name == "nc8_ds_tanh":
+        vs = C.newton_cotes(8, 0.5, renormalize=True)
+        c = C.cavity_case(18, vs, wall=C.BC_DIFFUSE, grid=C.tanh_grid(18, 18), tau=0.3, lid=0.1)
+        return _perturb(c, 11)
+    if name == "nc16_ds_couette":
+        vs = C.newton_cotes(16, 0.5, renormalize=True)
+        c = C.couette_case(20, vs, tau=C.kn_to_tau(1.0, 0.5), U=0.146, cfl=0.25,
+                           grid=C.Grid(C.uniform_grid(20, 20).xf, C.tanh_faces(20)))
+        return _perturb(c, 12)
+    if name == "nc28_cavity_kn1":
+        # rarefied lid-driven cavity, reduced size: Newton-Cotes 28 x 28 on
+        # [-4, 4] sqrt(RT), tanh cells, Kn = 1, diffuse walls, lid 0.146
+        vs = C.newton_cotes(28, 0.5)
+        c = C.cavity_case(24, vs, wall=C.BC_DIFFUSE, grid=C.tanh_grid(24, 24),
+                          tau=C.kn_to_tau(1.0, 0.5), lid=0.146, cfl=0.25)
+        return c
     raise KeyError(name)
 
 
@@ -80,9 +96,13 @@ FP64_CASES = ["tgv32_d2q9", "tgv_ragged_37x29", "tgv24_d2q37", "tgv_tau_field", 
               "cavity_bb_tanh", "couette_ds_d2q9", "cavity_ds_d2q37_tanh", "cavity_bb_d2q37_48"]
 
 
+def _allow(case):
+    return abs(case.vs.moment_defect()["sum_w_minus_1"]) > 1e-10
+
+
 def _pair(case, kappa, **kw):
     o = oracle.Oracle(case, literal_taylor=(kappa == 1.0))
-    s = dugks.Solver(case, dugks.FP64, taylor_quad=kappa, **kw)
+    s = dugks.Solver(case, dugks.FP64, taylor_quad=kappa, allow_defect=_allow(case), **kw)
     s.init_equilibrium(case.rho, case.ux, case.uy)
     return o, s
 
@@ -216,3 +236,72 @@ def test_deterministic_replay():
         outs.append(s.get_fhat())
         s.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+# ---------------------------------------------------------------------------
+# any-size velocity-set kernels (q split into chunks across workgroups)
+# ---------------------------------------------------------------------------
+GENERIC_CASES = [("tgv32_d2q9", True), ("couette_ds_d2q9", True), ("tgv_tau_field", True),
+                 ("cavity_ds_d2q37_tanh", True), ("nc8_ds_tanh", False), ("nc16_ds_couette", False),
+                 ("nc28_cavity_kn1", False)]
+
+
+@pytest.mark.parametrize("name,force", GENERIC_CASES)
+def test_anysize_fp64_one_step_every_element(name, force):
+    case = _mk(name)
+    say(f"[gpu] any-size fp64 one step {name} Q={case.vs.nq}")
+    o, s = _pair(case, 1.0, force_generic=force)
+    assert "any-size" in s.describe()
+    want = o.step(o.init_fhat())
+    s.step(1)
+    s.sync()
+    got = s.get_fhat()
+    err = np.abs(got - want).max() / np.abs(want).max()
+    say(f"    max rel err {err:.2e}  ({s.describe()})")
+    assert err < 1e-13
+    s.close()
+
+
+@pytest.mark.parametrize("name,force,steps", [("tgv32_d2q9", True, 100), ("nc8_ds_tanh", False, 40),
+                                              ("nc28_cavity_kn1", False, 20)])
+def test_anysize_fp64_many_steps(name, force, steps):
+    case = _mk(name)
+    say(f"[gpu] any-size fp64 {steps} steps {name}")
+    o, s = _pair(case, 1.0, force_generic=force)
+    fh = o.run(o.init_fhat(), steps)
+    ro, uxo, uyo = o.moments(fh)
+    s.step(steps)
+    s.sync()
+    r, ux, uy = s.moments()
+    us = max(np.abs(uxo).max(), np.abs(uyo).max())
+    e_u = max(np.abs(ux - uxo).max(), np.abs(uy - uyo).max()) / us
+    e_rho = np.abs(r - ro).max() / np.abs(ro).max()
+    say(f"    rho {e_rho:.2e}  u {e_u:.2e}")
+    assert e_rho < 1e-12 and e_u < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("name,steps", [("nc16_ds_couette", 100), ("nc28_cavity_kn1", 40)])
+def test_anysize_fp32_delta(name, steps):
+    case = _mk(name)
+    say(f"[gpu] any-size fp32-delta {steps} steps {name}")
+    o = oracle.Oracle(case)
+    fh = o.run(o.init_fhat(), steps)
+    ro, uxo, uyo = o.moments(fh)
+    s = dugks.Solver(case, dugks.FP32_DELTA, allow_defect=_allow(case))
+    s.init_equilibrium(case.rho, case.ux, case.uy)
+    s.step(steps)
+    s.sync()
+    r, ux, uy = s.moments()
+    us = max(np.abs(uxo).max(), np.abs(uyo).max())
+    e_u = max(np.abs(ux - uxo).max(), np.abs(uy - uyo).max()) / us
+    say(f"    u {e_u:.2e}  rho {np.abs(r - ro).max():.2e}")
+    assert e_u < 1e-5
+    s.close()
+
+
+def test_anysize_rejects_bounce_back():
+    case = C.cavity_case(16, C.newton_cotes(8, 0.5, renormalize=True), tau=0.2)
+    with pytest.raises(dugks.DugksError) as e:
+        dugks.Solver(case)
+    assert e.value.code == -7
