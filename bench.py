@@ -36,6 +36,10 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 companion run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--tile", default="", help="tile as TXxTY")
+    ap.add_argument("--workload", default="tgv", choices=["tgv", "batched", "rarefied"],
+                    help="tgv: Taylor-Green (headline); batched: 64 uneven cavities in one graph "
+                         "launch per step; rarefied: Newton-Cotes cavity on stretched cells")
+    ap.add_argument("--nc", type=int, default=101, help="Newton-Cotes points per axis (rarefied)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -88,6 +92,91 @@ def time_run(case, precision, steps, warmup, tile):
             "mass": float(r.mean())}
 
 
+def run_batched(args):
+    """64 independent cavities (D2Q9 bounce-back or Newton-Cotes 16^2..40^2
+    diffuse walls, 32^2..256^2 cells, Kn log-uniform in [1e-3, 10], seed 4),
+    FP32-delta, one graph launch per step, tuned tiles."""
+    import torch
+    from paper_1709_05458_amd import cases as C, dugks, tune
+    cases = C.batch_cases(64, seed=4)
+    tiles = tune.tiles_for(cases, dugks.FP32_DELTA)
+    b = dugks.BatchSolver(cases, dugks.FP32_DELTA, tiles=tiles)
+    for inst, c in zip(b.instances, cases):
+        inst.init_equilibrium(c.rho, c.ux, c.uy)
+    b.step(args.warmup)
+    b.sync()
+    torch.cuda.synchronize()
+    b.prof_begin(args.steps + 4)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    b.step(args.steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    g_ms, g_n = b.prof_query(dugks.K_AUX)
+    b.sync()
+    pairs = sum(c.grid.nx * c.grid.ny * c.vs.nq for c in cases)
+    desc = b.describe()
+    b.close()
+    gcups = pairs / (ms * 1e-3) / 1e9
+    # algorithmic bytes of a step: lattice instances 5 elements per pair (stage A
+    # read + write, stage C two reads + write); any-size instances 7 (each stage
+    # reads its input twice)
+    lat_pairs = sum(c.grid.nx * c.grid.ny * c.vs.nq for c in cases if c.vs.name == "D2Q9")
+    step_bytes = 4 * (5 * lat_pairs + 7 * (pairs - lat_pairs))
+    achieved = step_bytes / (ms * 1e-3) / 1e9
+    return {
+        "metric": "G cell-velocity updates/s per DUGKS step (batched, FP32-delta) + %HBM peak",
+        "value": round(gcups, 3), "unit": "G cell-velocity updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched: 64 lid-driven cavities, 32^2..256^2 cells, D2Q9 or Newton-Cotes "
+                               "16^2..40^2, Kn 1e-3..10, seed 4, one graph launch per step",
+                   "pairs": pairs, "variant": desc},
+        "roofline": {"bound": "hbm", "kernel": "whole step (graph)", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": step_bytes, "launch_ms": round(g_ms, 5)},
+        "cpu_baseline": None,
+    }
+
+
+def run_rarefied(args):
+    """Rarefied lid-driven cavity: 128^2 tanh-stretched cells, Newton-Cotes
+    nc x nc velocities on [-4, 4] sqrt(RT), Kn = 1, diffuse walls, FP32-delta."""
+    import torch
+    from paper_1709_05458_amd import cases as C, dugks
+    n = args.n if args.n != 2048 else 128
+    vs = C.newton_cotes(args.nc, 0.5)
+    case = C.cavity_case(n, vs, wall=C.BC_DIFFUSE, grid=C.tanh_grid(n, n), tau=C.kn_to_tau(1.0, 0.5),
+                         lid=0.146, cfl=0.25)
+    out = {}
+    for prec, name in ((dugks.FP32_DELTA, "fp32"), (dugks.FP64, "fp64")):
+        s = dugks.Solver(case, prec, allow_defect=True)
+        s.init_equilibrium(case.rho, case.ux, case.uy)
+        s.step(2)
+        s.sync()
+        steps = max(3, args.steps // 10)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        pairs = n * n * vs.nq
+        out[name] = {"value": round(pairs / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 4),
+                     "variant": s.describe()}
+        s.close()
+    return {"metric": "G cell-velocity updates/s per DUGKS step (rarefied cavity)",
+            "value": out["fp32"]["value"], "unit": "G cell-velocity updates/s", "n_gpus": 1,
+            "steps": max(3, args.steps // 10), "warmup": 2, "ms_per_step": out["fp32"]["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"rarefied cavity {n}x{n} tanh cells, Newton-Cotes {args.nc}x{args.nc}, "
+                                   "Kn 1, diffuse walls"},
+            "fp64": out["fp64"], "roofline": None, "cpu_baseline": None}
+
+
 def cpu_baseline(lattice):
     """The oracle as it stands on the host cores, on a bounded sample of the
     same workload (Taylor-Green, same velocity set, 256 x 256, a few steps)."""
@@ -119,6 +208,12 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.workload == "batched":
+        print(json.dumps(run_batched(args)))
+        return
+    if args.workload == "rarefied":
+        print(json.dumps(run_rarefied(args)))
         return
     tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
     case = make_case(args.n, args.lattice)

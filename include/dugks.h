@@ -153,6 +153,20 @@ int dugks_backward(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
                    const double *dL_drho, const double *dL_du,
                    double *dL_df0, double *dL_dtau, int mem);
 
+/* Batch of independent instances (uneven grids, velocity sets, relaxation
+ * times and walls) stepped together: every dugks_step launches one kernel
+ * per tile kind for all lattice instances and one per phase for all
+ * any-size instances, replayed from a HIP graph captured on the first step
+ * (a step is one graph launch).  All descriptors share
+ * precision and stream; instances of one lattice kind, and all any-size
+ * instances, need tiles with the same cell count.  Instance handles from
+ * dugks_batch_instance are owned by the batch and serve set_state,
+ * init_equilibrium, moments and get_state; stepping one alone makes the
+ * next batch step fail with DUGKS_EINVAL.  dugks_sync checks every instance. */
+int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out);
+int dugks_batch_size(dugks_t *h, int *n);
+int dugks_batch_instance(dugks_t *h, int k, dugks_t **inst);
+
 /* Kernel timing by HIP events recorded around each launch on the stream.
  * prof_begin clears the record (room for max_launches launches); after the
  * stream is synchronised, prof_query returns the mean duration in ms and the

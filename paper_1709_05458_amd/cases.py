@@ -438,3 +438,33 @@ def perturbed_tau(tau0: float, shape, rel: float, seed: int) -> np.ndarray:
     """tau0 * (1 + rel * N(0,1)) per cell, seeded."""
     z = normal(seed, int(np.prod(shape))).reshape(shape)
     return tau0 * (1.0 + rel * z)
+
+
+def batch_cases(n: int = 64, seed: int = 4, nmin: int = 32, nmax: int = 256,
+                ncmin: int = 16, ncmax: int = 40, kn_lo: float = -3.0, kn_hi: float = 1.0) -> list:
+    """Independent lid-driven cavity instances of uneven size (seeded):
+    side N ~ U{nmin..nmax}; velocity set D2Q9 (probability 1/2; bounce-back,
+    RT = 1/3, CFL 0.5) or an n x n Newton-Cotes grid, n ~ U{ncmin..ncmax}
+    (moment-renormalised; diffuse walls, RT = 0.5, CFL 0.25); Kn log-uniform
+    in [10^kn_lo, 10^kn_hi], tau = Kn sqrt(2 / (pi RT)); lid Ma 0.1 against
+    sqrt(3 RT); dt = min(CFL dx / C, 8 tau), which keeps dt/tau <= 8."""
+    u = uniform01(seed, 4 * n).reshape(n, 4)
+    out = []
+    for k in range(n):
+        N = nmin + min(nmax - nmin, int(u[k, 0] * (nmax - nmin + 1)))
+        kn = 10.0 ** (kn_lo + (kn_hi - kn_lo) * u[k, 2])
+        if u[k, 1] < 0.5:
+            RT, cfl, wall = 1.0 / 3.0, 0.5, BC_BOUNCE_BACK
+            vs = d2q9(RT)
+        else:
+            RT, cfl, wall = 0.5, 0.25, BC_DIFFUSE
+            nc = ncmin + min(ncmax - ncmin, int(u[k, 3] * (ncmax - ncmin + 1)))
+            vs = newton_cotes(nc, RT, renormalize=True)
+        tau = kn_to_tau(kn, RT)
+        lid = 0.1 * math.sqrt(3.0 * RT)
+        c = cavity_case(N, vs, wall=wall, tau=tau, lid=lid, cfl=cfl, RT=RT)
+        c.dt = min(c.dt, 8.0 * tau)
+        c.name = f"batch{k}_{N}_{vs.name}_Kn{kn:.3g}"
+        c.meta.update({"Kn": kn, "cfl": cfl})
+        out.append(c)
+    return out

@@ -37,6 +37,31 @@ struct dugks {
     int prof_max = 0, prof_n = 0;
     bool prof_on = false;
     std::string variant;
+    // batch of instances (dugks_create_batch): the handle owns the instances
+    // and steps them with batched launches replayed from captured graphs
+    struct Batch;
+    Batch *batch = nullptr;
+};
+
+struct dugks::Batch {
+    std::vector<dugks *> inst;
+    bool delta = false;
+    SweepParams *d_params = nullptr;
+    StageIO *d_io = nullptr;        // [parity][stage][instance]
+    LQStage *d_lq = nullptr;        // [parity][stage][instance]
+    struct Group {                  // one lattice kind
+        int lat = 0;
+        int nthreads = 0;
+        size_t smem = 0;
+        int4 *fast = nullptr, *gen = nullptr;
+        int nfast = 0, ngen = 0;
+    };
+    std::vector<Group> groups;
+    int4 *lq_tiles = nullptr, *lq_faces = nullptr, *lq_cells = nullptr;
+    int nlq_tiles = 0, nlq_faces = 0, nlq_cells = 0, lq_threads = 0;
+    size_t lq_smem = 0;
+    hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [parity][1 or 2 steps]
+    std::vector<void *> allocs;
 };
 
 static thread_local std::string g_err;
@@ -245,6 +270,14 @@ const char *dugks_last_error_message(void) { return g_err.c_str(); }
 int dugks_destroy(dugks_t *h)
 {
     if (!h) return DUGKS_OK;
+    if (h->batch) {
+        for (auto &pe : h->batch->exec)
+            for (auto &e : pe)
+                if (e) (void)hipGraphExecDestroy(e);
+        for (dugks *c : h->batch->inst) dugks_destroy(c);
+        for (void *p : h->batch->allocs) (void)hipFree(p);
+        delete h->batch;
+    }
     for (auto &e : h->ev) (void)hipEventDestroy(e);
     for (void *p : h->allocs) (void)hipFree(p);
     delete h;
@@ -432,7 +465,14 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
         return fail(DUGKS_EINVAL, "tile too large for LDS");
     }
     {
-        hipError_t e = h->lat == 0 ? set_lq_smem(h->delta, smem) : set_stage_smem(h->lat, h->delta, smem);
+        // the dynamic-LDS limit is a per-kernel attribute: only ever raise it
+        static size_t raised[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+        size_t &mx = raised[h->lat == 0 ? 0 : (h->lat == 9 ? 1 : 2)][h->delta ? 1 : 0];
+        hipError_t e = hipSuccess;
+        if (smem > mx) {
+            e = h->lat == 0 ? set_lq_smem(h->delta, smem) : set_stage_smem(h->lat, h->delta, smem);
+            if (e == hipSuccess) mx = smem;
+        }
         if (e != hipSuccess) {
             delete h;
             return fail(DUGKS_EDEVICE, std::string("LDS size: ") + hipGetErrorString(e));
@@ -636,9 +676,12 @@ static int record(dugks *h, int kind, bool start)
     return DUGKS_OK;
 }
 
+static int batch_step(dugks_t *h, int nsteps);
+
 int dugks_step(dugks_t *h, int nsteps)
 {
     if (!h || nsteps < 0) return fail(DUGKS_EINVAL, "bad arguments");
+    if (h->batch) return batch_step(h, nsteps);
     for (int s = 0; s < nsteps; s++) {
         void *X = h->state[h->cur], *Y = h->state[1 - h->cur];
         int rc;
@@ -741,6 +784,14 @@ int dugks_set_tau(dugks_t *h, const double *tau, int mem)
 int dugks_sync(dugks_t *h)
 {
     if (!h) return fail(DUGKS_EINVAL, "null handle");
+    if (h->batch) {
+        HIPCHECK(hipStreamSynchronize(h->stream));
+        for (dugks *c : h->batch->inst) {
+            int rc = dugks_sync(c);
+            if (rc) return rc;
+        }
+        return DUGKS_OK;
+    }
     HIPCHECK(hipMemsetAsync(h->d_bad, 0, sizeof(int), h->stream));
     HIPCHECK(launch_moments(h->p, h->delta, h->state[h->cur], nullptr, nullptr, nullptr, h->d_bad,
                             h->stream));
@@ -786,6 +837,220 @@ int dugks_prof_end(dugks_t *h)
 {
     if (!h) return fail(DUGKS_EINVAL, "null handle");
     h->prof_on = false;
+    return DUGKS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+extern "C++" {
+template <class T>
+static int batch_upload(dugks::Batch *b, const std::vector<T> &v, T **dst)
+{
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(T) * (v.empty() ? 1 : v.size()));
+    if (e != hipSuccess) return fail(DUGKS_ENOMEM, "batch table");
+    b->allocs.push_back(p);
+    if (!v.empty()) HIPCHECK(hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    *dst = (T *)p;
+    return DUGKS_OK;
+}
+}  // extern "C++"
+
+int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
+{
+    if (!out || !descs || n < 1) return fail(DUGKS_EINVAL, "bad arguments");
+    *out = nullptr;
+    for (int k = 0; k < n; k++)
+        if (descs[k].precision != descs[0].precision || descs[k].stream != descs[0].stream)
+            return fail(DUGKS_EINVAL, "instances of a batch share precision and stream");
+    dugks *h = new dugks();
+    h->stream = (hipStream_t)descs[0].stream;
+    h->delta = descs[0].precision == DUGKS_FP32_DELTA;
+    h->batch = new dugks::Batch();
+    dugks::Batch *b = h->batch;
+    b->delta = h->delta;
+    int rc;
+    for (int k = 0; k < n; k++) {
+        dugks_t *c = nullptr;
+        if ((rc = dugks_create(&descs[k], &c))) {
+            const std::string m = g_err;
+            dugks_destroy(h);
+            return fail(rc, "instance " + std::to_string(k) + ": " + m);
+        }
+        b->inst.push_back(c);
+    }
+    // parameter table and per-(parity, stage) buffer tables
+    std::vector<SweepParams> P;
+    std::vector<StageIO> io(4 * (size_t)n);
+    std::vector<LQStage> lq(4 * (size_t)n);
+    for (int k = 0; k < n; k++) {
+        dugks *c = b->inst[k];
+        P.push_back(c->p);
+        for (int par = 0; par < 2; par++) {
+            void *X = c->state[par], *Y = c->state[1 - par];
+            io[(par * 2 + 0) * n + k] = StageIO{X, nullptr, c->G, c->coefA, c->h1};
+            io[(par * 2 + 1) * n + k] = StageIO{c->G, X, Y, c->coefC, c->h2};
+            lq[(par * 2 + 0) * n + k] = LQStage{X, nullptr, c->G, c->mom_state, nullptr, c->face_part,
+                                                c->face_mom, c->cell_part, c->mom_G, c->h1, 0};
+            lq[(par * 2 + 1) * n + k] = LQStage{c->G, X, Y, c->mom_G, c->mom_state, c->face_part,
+                                                c->face_mom, c->cell_part, c->mom_state, c->h2, 1};
+        }
+    }
+    if ((rc = batch_upload(b, P, &b->d_params)) || (rc = batch_upload(b, io, &b->d_io)) ||
+        (rc = batch_upload(b, lq, &b->d_lq))) {
+        dugks_destroy(h);
+        return rc;
+    }
+    // work lists
+    for (int lat : {9, 37}) {
+        dugks::Batch::Group g;
+        g.lat = lat;
+        std::vector<int4> fast, gen;
+        for (int k = 0; k < n; k++) {
+            dugks *c = b->inst[k];
+            if (c->lat != lat) continue;
+            const SweepParams &p = c->p;
+            const int nt = p.tile_x * p.tile_y;
+            if (g.nthreads == 0) g.nthreads = nt;
+            if (nt != g.nthreads) {
+                dugks_destroy(h);
+                return fail(DUGKS_EINVAL, "instances of one lattice in a batch need tiles of equal size");
+            }
+            g.smem = std::max(g.smem, c->elem * (size_t)p.nq * (p.tile_x + 4) * (p.tile_y + 4));
+            const int gx = (p.nx + p.tile_x - 1) / p.tile_x, gy = (p.ny + p.tile_y - 1) / p.tile_y;
+            for (int ty = 0; ty < gy; ty++)
+                for (int tx = 0; tx < gx; tx++) {
+                    const int i0 = tx * p.tile_x, j0 = ty * p.tile_y;
+                    const bool isfast = p.uniform && (p.perx || (i0 >= 2 && i0 + p.tile_x <= p.nx - 2)) &&
+                                        (p.pery || (j0 >= 2 && j0 + p.tile_y <= p.ny - 2));
+                    (isfast ? fast : gen).push_back(make_int4(k, tx, ty, 0));
+                }
+        }
+        if (g.nthreads == 0) continue;
+        g.nfast = (int)fast.size();
+        g.ngen = (int)gen.size();
+        if ((rc = batch_upload(b, fast, &g.fast)) || (rc = batch_upload(b, gen, &g.gen))) {
+            dugks_destroy(h);
+            return rc;
+        }
+        b->groups.push_back(g);
+    }
+    {
+        std::vector<int4> tiles, faces, cells;
+        for (int k = 0; k < n; k++) {
+            dugks *c = b->inst[k];
+            if (c->lat != 0) continue;
+            const SweepParams &p = c->p;
+            const int nt = p.tile_x * p.tile_y;
+            if (b->lq_threads == 0) b->lq_threads = nt;
+            if (nt != b->lq_threads) {
+                dugks_destroy(h);
+                return fail(DUGKS_EINVAL, "any-size instances in a batch need tiles of equal size");
+            }
+            b->lq_smem = std::max(b->lq_smem, lq_smem_bytes(p, b->delta));
+            const int ntile = ((p.nx + p.tile_x - 1) / p.tile_x) * ((p.ny + p.tile_y - 1) / p.tile_y);
+            for (int ch = 0; ch < p.lq_nchunk; ch++)
+                for (int t = 0; t < ntile; t++) tiles.push_back(make_int4(k, t, ch, 0));
+            const long long nface = (long long)(p.nx + 1) * p.ny + (long long)p.nx * (p.ny + 1);
+            for (long long f = 0; f < (nface + 255) / 256; f++) faces.push_back(make_int4(k, (int)f, 0, 0));
+            for (long long f = 0; f < (p.ncell + 255) / 256; f++) cells.push_back(make_int4(k, (int)f, 0, 0));
+        }
+        b->nlq_tiles = (int)tiles.size();
+        b->nlq_faces = (int)faces.size();
+        b->nlq_cells = (int)cells.size();
+        if ((rc = batch_upload(b, tiles, &b->lq_tiles)) || (rc = batch_upload(b, faces, &b->lq_faces)) ||
+            (rc = batch_upload(b, cells, &b->lq_cells))) {
+            dugks_destroy(h);
+            return rc;
+        }
+    }
+    char buf[160];
+    long long pairs = 0;
+    for (dugks *c : b->inst) pairs += c->p.ncell * c->p.nq;
+    snprintf(buf, sizeof buf, "batch of %d instances (%lld pairs), %s, %d lattice groups, %d any-size tiles",
+             n, pairs, b->delta ? "fp32-delta" : "fp64", (int)b->groups.size(), b->nlq_tiles);
+    h->variant = buf;
+    *out = h;
+    return DUGKS_OK;
+}
+
+int dugks_batch_size(dugks_t *h, int *n)
+{
+    if (!h || !h->batch || !n) return fail(DUGKS_EINVAL, "not a batch");
+    *n = (int)h->batch->inst.size();
+    return DUGKS_OK;
+}
+
+int dugks_batch_instance(dugks_t *h, int k, dugks_t **inst)
+{
+    if (!h || !h->batch || !inst || k < 0 || k >= (int)h->batch->inst.size())
+        return fail(DUGKS_EINVAL, "bad batch instance");
+    *inst = h->batch->inst[k];
+    return DUGKS_OK;
+}
+
+// one step of every instance, starting from state parity `par`
+static int batch_enqueue_step(dugks *h, int par)
+{
+    dugks::Batch *b = h->batch;
+    const int n = (int)b->inst.size();
+    for (int stage = 0; stage < 2; stage++) {
+        const StageIO *io = b->d_io + (size_t)(par * 2 + stage) * n;
+        for (const auto &g : b->groups)
+            HIPCHECK(launch_stage_batched(stage, g.lat, b->delta, b->d_params, io, g.fast, g.nfast, g.gen,
+                                          g.ngen, g.nthreads, g.smem, h->stream));
+        if (b->nlq_tiles)
+            HIPCHECK(launch_lq_stage_batched(b->delta, b->d_params, b->d_lq + (size_t)(par * 2 + stage) * n,
+                                             b->lq_tiles, b->nlq_tiles, b->lq_faces, b->nlq_faces,
+                                             b->lq_cells, b->nlq_cells, b->lq_threads, b->lq_smem, h->stream));
+    }
+    return DUGKS_OK;
+}
+
+static int batch_graph(dugks *h, int par, int steps, hipGraphExec_t *exec)
+{
+    if (*exec) return DUGKS_OK;
+    hipStream_t s = h->stream;
+    bool own = false;
+    if (!s) {   // stream capture needs a real stream
+        HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        own = true;
+    }
+    hipStream_t keep = h->stream;
+    h->stream = s;
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = DUGKS_OK;
+    for (int k = 0; k < steps && rc == DUGKS_OK; k++) rc = batch_enqueue_step(h, (par + k) & 1);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    h->stream = keep;
+    if (own) (void)hipStreamDestroy(s);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(DUGKS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(DUGKS_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    return DUGKS_OK;
+}
+
+static int batch_step(dugks_t *h, int nsteps)
+{
+    dugks::Batch *b = h->batch;
+    const int par = b->inst[0]->cur;
+    for (dugks *c : b->inst)
+        if (c->cur != par) return fail(DUGKS_EINVAL, "instances of the batch were stepped separately");
+    int cur = par, rc;
+    for (int done = 0; done < nsteps;) {
+        const int k = (nsteps - done >= 2) ? 2 : 1;
+        if ((rc = batch_graph(h, cur, k, &b->exec[cur][k - 1]))) return rc;
+        if ((rc = record(h, KC_AUX, true))) return rc;
+        HIPCHECK(hipGraphLaunch(b->exec[cur][k - 1], h->stream));
+        if ((rc = record(h, KC_AUX, false))) return rc;
+        cur = (cur + k) & 1;
+        done += k;
+    }
+    for (dugks *c : b->inst) c->cur = cur;
     return DUGKS_OK;
 }
 

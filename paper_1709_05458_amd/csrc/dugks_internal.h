@@ -80,6 +80,15 @@ struct LQStage {
     int stage;              // 0: stage A, 1: stage C
 };
 
+// Per-instance buffers of one stage of the lattice kernels (batched launches).
+struct StageIO {
+    const void *X;      // stage input
+    const void *F;      // stage C: fhat(t_n)
+    void *out;          // stage output
+    const void *coef;   // fast-path face weights of the stage
+    double h;           // characteristic step of the stage
+};
+
 // Kernel classes for event timing.
 enum KernelClass { KC_STAGE_A = 0, KC_STAGE_C = 1, KC_AUX = 2, KC_COUNT = 3 };
 
@@ -89,6 +98,16 @@ hipError_t launch_stage(int stage, int lat, bool delta, const SweepParams &p, do
                         const void *X, const void *F, void *out, const void *coef,
                         hipStream_t s);
 hipError_t set_stage_smem(int lat, bool delta, size_t bytes);
+// Many instances in one launch per tile kind: work items (instance, tile x, tile y, 0).
+hipError_t launch_stage_batched(int stage, int lat, bool delta, const SweepParams *P, const StageIO *io,
+                                const int4 *work_fast, int nfast, const int4 *work_gen, int ngen,
+                                int nthreads, size_t smem, hipStream_t s);
+// Any-size kernels over many instances: work items (instance, tile, chunk, 0) for
+// the two tile kernels and (instance, block, 0, 0) for the two reductions.
+hipError_t launch_lq_stage_batched(bool delta, const SweepParams *P, const LQStage *A,
+                                   const int4 *work_tiles, int ntiles, const int4 *work_faces, int nfaces,
+                                   const int4 *work_cells, int ncells, int nthreads, size_t smem,
+                                   hipStream_t s);
 
 // Large velocity sets (sweep_large.hip).  part < 0: all four kernels of the stage.
 hipError_t launch_lq_stage(bool delta, const SweepParams &p, const LQStage &a, hipStream_t s, int part);

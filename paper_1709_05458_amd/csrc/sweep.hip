@@ -316,9 +316,9 @@ __device__ __forceinline__ bool tile_is_fast(const SweepParams &p, int i0, int j
 }
 
 template <class Lat, class S, bool DELTA, int STAGE, bool GENERAL>
-__global__ void __launch_bounds__(512)
-sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
-            const S *__restrict__ F, S *__restrict__ out, const S *__restrict__ coef)
+__device__ __forceinline__ void
+sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
+                 const S *__restrict__ F, S *__restrict__ out, const S *__restrict__ coef, int tx, int ty)
 {
     constexpr int Q = Lat::Q;
     using Seq = std::make_integer_sequence<int, Q>;
@@ -326,10 +326,7 @@ sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
     S *lds = reinterpret_cast<S *>(smem_raw);
 
     const int TX = p.tile_x, TY = p.tile_y;
-    int tx, ty;
-    tile_of_block(p, tx, ty);
     const int i0 = tx * TX, j0 = ty * TY;
-    if (tile_is_fast(p, i0, j0, TX, TY) == GENERAL) return;   // whole block: no barrier skipped
 
     const int HX = TX + 4;
     const int plane = HX * (TY + 4);
@@ -586,6 +583,33 @@ sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
     }(Seq{});
 }
 
+// Single instance: tiles from the block index (XCD-aware order); each kind of
+// tile is handled by its own instantiation.
+template <class Lat, class S, bool DELTA, int STAGE, bool GENERAL>
+__global__ void __launch_bounds__(512)
+sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
+            const S *__restrict__ F, S *__restrict__ out, const S *__restrict__ coef)
+{
+    int tx, ty;
+    tile_of_block(p, tx, ty);
+    if (tile_is_fast(p, tx * p.tile_x, ty * p.tile_y, p.tile_x, p.tile_y) == GENERAL) return;
+    sweep_small_body<Lat, S, DELTA, STAGE, GENERAL>(p, h, X, F, out, coef, tx, ty);
+}
+
+// Many instances in one launch: block b works on work[b] = (instance, tile x,
+// tile y), with the instance's parameters and buffers read from device tables.
+template <class Lat, class S, bool DELTA, int STAGE, bool GENERAL>
+__global__ void __launch_bounds__(512)
+sweep_small_batched(const SweepParams *__restrict__ P, const StageIO *__restrict__ io,
+                    const int4 *__restrict__ work)
+{
+    const int4 w = work[blockIdx.x];
+    const SweepParams &p = P[w.x];
+    const StageIO &a = io[w.x];
+    sweep_small_body<Lat, S, DELTA, STAGE, GENERAL>(p, a.h, (const S *)a.X, (const S *)a.F, (S *)a.out,
+                                                   (const S *)a.coef, w.y, w.z);
+}
+
 // ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
@@ -612,15 +636,53 @@ static hipError_t launch_t(const SweepParams &p, double h, const void *X, const 
 template <class Lat, class S, bool DELTA>
 static hipError_t smem_t(size_t bytes)
 {
-    const void *fns[4] = {(const void *)sweep_small<Lat, S, DELTA, 0, false>,
+    const void *fns[8] = {(const void *)sweep_small<Lat, S, DELTA, 0, false>,
                           (const void *)sweep_small<Lat, S, DELTA, 1, false>,
                           (const void *)sweep_small<Lat, S, DELTA, 0, true>,
-                          (const void *)sweep_small<Lat, S, DELTA, 1, true>};
+                          (const void *)sweep_small<Lat, S, DELTA, 1, true>,
+                          (const void *)sweep_small_batched<Lat, S, DELTA, 0, false>,
+                          (const void *)sweep_small_batched<Lat, S, DELTA, 1, false>,
+                          (const void *)sweep_small_batched<Lat, S, DELTA, 0, true>,
+                          (const void *)sweep_small_batched<Lat, S, DELTA, 1, true>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+template <class Lat, class S, bool DELTA, int STAGE>
+static hipError_t launch_batched_t(const SweepParams *P, const StageIO *io, const int4 *work, int nfast,
+                                   const int4 *work_gen, int ngen, int nthreads, size_t smem, hipStream_t s)
+{
+    if (nfast > 0)
+        hipLaunchKernelGGL((sweep_small_batched<Lat, S, DELTA, STAGE, false>), dim3(nfast), dim3(nthreads),
+                           smem, s, P, io, work);
+    if (ngen > 0)
+        hipLaunchKernelGGL((sweep_small_batched<Lat, S, DELTA, STAGE, true>), dim3(ngen), dim3(nthreads),
+                           smem, s, P, io, work_gen);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_batched(int stage, int lat, bool delta, const SweepParams *P, const StageIO *io,
+                                const int4 *work_fast, int nfast, const int4 *work_gen, int ngen,
+                                int nthreads, size_t smem, hipStream_t s)
+{
+#define DUGKS_LB(LAT, S_, D_)                                                                   \
+    return stage == 0 ? launch_batched_t<LAT, S_, D_, 0>(P, io, work_fast, nfast, work_gen, ngen, \
+                                                         nthreads, smem, s)                     \
+                      : launch_batched_t<LAT, S_, D_, 1>(P, io, work_fast, nfast, work_gen, ngen, \
+                                                         nthreads, smem, s)
+    if (lat == 9) {
+        if (delta) DUGKS_LB(LatD2Q9, float, true);
+        DUGKS_LB(LatD2Q9, double, false);
+    }
+    if (lat == 37) {
+        if (delta) DUGKS_LB(LatD2Q37, float, true);
+        DUGKS_LB(LatD2Q37, double, false);
+    }
+#undef DUGKS_LB
+    return hipErrorInvalidValue;
 }
 
 hipError_t set_stage_smem(int lat, bool delta, size_t bytes)

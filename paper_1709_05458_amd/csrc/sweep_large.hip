@@ -558,6 +558,65 @@ __global__ void __launch_bounds__(256) lq_cell_reduce(const SweepParams p, const
     lq_cell_reduce_body(p, a, DELTA, (long long)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
+template <class S, bool DELTA>
+__global__ void __launch_bounds__(256) lq_faces_batched(const SweepParams *__restrict__ P,
+                                                        const LQStage *__restrict__ A,
+                                                        const int4 *__restrict__ work)
+{
+    const int4 w = work[blockIdx.x];
+    lq_faces_body<S, DELTA>(P[w.x], A[w.x], w.y, w.z);
+}
+
+template <class S, bool DELTA>
+__global__ void __launch_bounds__(256) lq_update_batched(const SweepParams *__restrict__ P,
+                                                         const LQStage *__restrict__ A,
+                                                         const int4 *__restrict__ work)
+{
+    const int4 w = work[blockIdx.x];
+    lq_update_body<S, DELTA>(P[w.x], A[w.x], w.y, w.z);
+}
+
+template <bool DELTA>
+__global__ void __launch_bounds__(256) lq_face_reduce_batched(const SweepParams *__restrict__ P,
+                                                              const LQStage *__restrict__ A,
+                                                              const int4 *__restrict__ work)
+{
+    const int4 w = work[blockIdx.x];
+    lq_face_reduce_body(P[w.x], A[w.x], DELTA, (long long)w.y * blockDim.x + threadIdx.x);
+}
+
+template <bool DELTA>
+__global__ void __launch_bounds__(256) lq_cell_reduce_batched(const SweepParams *__restrict__ P,
+                                                              const LQStage *__restrict__ A,
+                                                              const int4 *__restrict__ work)
+{
+    const int4 w = work[blockIdx.x];
+    lq_cell_reduce_body(P[w.x], A[w.x], DELTA, (long long)w.y * blockDim.x + threadIdx.x);
+}
+
+template <class S, bool DELTA>
+static hipError_t lq_batched_t(const SweepParams *P, const LQStage *A, const int4 *wt, int nt,
+                               const int4 *wf, int nf, const int4 *wc, int nc, int nthreads, size_t smem,
+                               hipStream_t s)
+{
+    if (nt > 0) hipLaunchKernelGGL((lq_faces_batched<S, DELTA>), dim3(nt), dim3(nthreads), smem, s, P, A, wt);
+    if (nf > 0) hipLaunchKernelGGL((lq_face_reduce_batched<DELTA>), dim3(nf), dim3(256), 0, s, P, A, wf);
+    if (nt > 0) hipLaunchKernelGGL((lq_update_batched<S, DELTA>), dim3(nt), dim3(nthreads), smem, s, P, A, wt);
+    if (nc > 0) hipLaunchKernelGGL((lq_cell_reduce_batched<DELTA>), dim3(nc), dim3(256), 0, s, P, A, wc);
+    return hipGetLastError();
+}
+
+hipError_t launch_lq_stage_batched(bool delta, const SweepParams *P, const LQStage *A,
+                                   const int4 *work_tiles, int ntiles, const int4 *work_faces, int nfaces,
+                                   const int4 *work_cells, int ncells, int nthreads, size_t smem,
+                                   hipStream_t s)
+{
+    return delta ? lq_batched_t<float, true>(P, A, work_tiles, ntiles, work_faces, nfaces, work_cells, ncells,
+                                             nthreads, smem, s)
+                 : lq_batched_t<double, false>(P, A, work_tiles, ntiles, work_faces, nfaces, work_cells,
+                                               ncells, nthreads, smem, s);
+}
+
 size_t lq_smem_bytes(const SweepParams &p, bool delta)
 {
     const size_t plane = (size_t)(p.tile_x + 4) * (p.tile_y + 4);
@@ -589,13 +648,17 @@ hipError_t launch_lq_stage(bool delta, const SweepParams &p, const LQStage &a, h
 
 hipError_t set_lq_smem(bool delta, size_t bytes)
 {
-    const void *fns[2];
+    const void *fns[4];
     if (delta) {
         fns[0] = (const void *)lq_faces<float, true>;
         fns[1] = (const void *)lq_update<float, true>;
+        fns[2] = (const void *)lq_faces_batched<float, true>;
+        fns[3] = (const void *)lq_update_batched<float, true>;
     } else {
         fns[0] = (const void *)lq_faces<double, false>;
         fns[1] = (const void *)lq_update<double, false>;
+        fns[2] = (const void *)lq_faces_batched<double, false>;
+        fns[3] = (const void *)lq_update_batched<double, false>;
     }
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

@@ -71,6 +71,9 @@ def lib():
             "dugks_prof_query": ([vp, ip, dp, POINTER(c_int)], ip),
             "dugks_prof_end": ([vp], ip),
             "dugks_describe": ([vp, c_char_p, ip], ip),
+            "dugks_create_batch": ([ip, POINTER(DugksDesc), POINTER(c_void_p)], ip),
+            "dugks_batch_size": ([vp, POINTER(c_int)], ip),
+            "dugks_batch_instance": ([vp, ip, POINTER(c_void_p)], ip),
             "dugks_strerror": ([ip], c_char_p),
             "dugks_last_error_message": ([], c_char_p),
         }
@@ -107,15 +110,69 @@ def _ptr_mem(x, dtype=np.float64):
     return c_void_p(a.ctypes.data), MEM_HOST, a
 
 
+def _default_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.cuda.current_stream().cuda_stream
+    except Exception:
+        pass
+    return None
+
+
+def make_desc(case, precision=FP64, taylor_quad=1.0, stream=None, tile=None, allow_defect=False,
+              tau=None, force_generic=False, d=None):
+    """Fill a DugksDesc from a cases.Case; returns (desc, arrays to keep alive)."""
+    g, vs = case.grid, case.vs
+    keep = [np.ascontiguousarray(g.xf, dtype=np.float64),
+            np.ascontiguousarray(g.yf, dtype=np.float64),
+            np.ascontiguousarray(vs.xi.reshape(-1), dtype=np.float64),
+            np.ascontiguousarray(vs.w, dtype=np.float64)]
+    d = DugksDesc() if d is None else d
+    d.nx, d.ny, d.nq = g.nx, g.ny, vs.nq
+    d.xf, d.yf = _dptr(keep[0]), _dptr(keep[1])
+    d.xi, d.w = _dptr(keep[2]), _dptr(keep[3])
+    d.RT, d.dt = vs.RT, case.dt
+    tau = case.tau if tau is None else tau
+    tau = np.asarray(tau, dtype=np.float64)
+    if tau.ndim == 0 or np.ptp(tau) == 0.0:
+        d.tau = POINTER(c_double)()
+        d.tau0 = float(tau.reshape(-1)[0])
+    else:
+        t = np.ascontiguousarray(tau.reshape(-1))
+        keep.append(t)
+        d.tau = _dptr(t)
+        d.tau0 = float(t.mean())
+    for k in range(4):
+        d.bc[k] = int(case.bc[k])
+        d.u_wall[k][0] = float(case.u_wall[k][0])
+        d.u_wall[k][1] = float(case.u_wall[k][1])
+    d.precision = precision
+    d.rho0 = float(case.rho0)
+    d.taylor_quad = taylor_quad
+    stream = _default_stream() if stream is None else stream
+    d.stream = c_void_p(stream) if stream else None
+    d.flags = (ALLOW_MOMENT_DEFECT if allow_defect else 0) | (FORCE_GENERIC if force_generic else 0)
+    if tile:
+        d.tile_x, d.tile_y = tile
+    return d, keep
+
+
 class Solver:
     """One T3S3-DUGKS solver instance (a dugks_t handle)."""
 
     def __init__(self, case, precision: int = FP64, taylor_quad: float = 1.0, stream=None,
-                 tile=None, allow_defect: bool = False, tau=None, force_generic: bool = False):
+                 tile=None, allow_defect: bool = False, tau=None, force_generic: bool = False,
+                 _borrowed=None):
         g, vs = case.grid, case.vs
         self.case = case
         self.nx, self.ny, self.nq = g.nx, g.ny, vs.nq
         self.ncell = g.nx * g.ny
+        self.precision = precision
+        self._owned = _borrowed is None
+        if _borrowed is not None:
+            self.h = _borrowed
+            return
         self._keep = [np.ascontiguousarray(g.xf, dtype=np.float64),
                       np.ascontiguousarray(g.yf, dtype=np.float64),
                       np.ascontiguousarray(vs.xi.reshape(-1), dtype=np.float64),
@@ -163,9 +220,9 @@ class Solver:
 
     # -- lifetime ------------------------------------------------------------
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and getattr(self, "_owned", True):
             lib().dugks_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -242,3 +299,62 @@ class Solver:
 
     def prof_end(self):
         check(lib().dugks_prof_end(self.h), "dugks_prof_end")
+
+
+class BatchSolver:
+    """Many independent instances stepped together (dugks_create_batch)."""
+
+    def __init__(self, cases, precision: int = FP32_DELTA, tiles=None, stream=None,
+                 allow_defect=None, taylor_quad: float = 1.0):
+        n = len(cases)
+        descs = (DugksDesc * n)()
+        self._keep = []
+        stream = _default_stream() if stream is None else stream
+        for k, c in enumerate(cases):
+            allow = (abs(c.vs.moment_defect()["sum_w_minus_1"]) > 1e-10) if allow_defect is None else allow_defect
+            _, keep = make_desc(c, precision, taylor_quad, stream, tiles[k] if tiles else None, allow,
+                                d=descs[k])
+            self._keep.append(keep)
+        self._descs = descs
+        h = c_void_p()
+        check(lib().dugks_create_batch(n, descs, byref(h)), "dugks_create_batch")
+        self.h = h
+        self.cases = list(cases)
+        self.instances = []
+        for k, c in enumerate(cases):
+            ih = c_void_p()
+            check(lib().dugks_batch_instance(h, k, byref(ih)), "dugks_batch_instance")
+            self.instances.append(Solver(c, precision, _borrowed=ih))
+
+    def step(self, n: int = 1):
+        check(lib().dugks_step(self.h, int(n)), "dugks_step")
+
+    def sync(self):
+        check(lib().dugks_sync(self.h), "dugks_sync")
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(256)
+        check(lib().dugks_describe(self.h, buf, 256), "dugks_describe")
+        return buf.value.decode()
+
+    def prof_begin(self, max_launches: int):
+        check(lib().dugks_prof_begin(self.h, int(max_launches)), "dugks_prof_begin")
+
+    def prof_query(self, kernel: int):
+        ms = c_double()
+        cnt = c_int()
+        check(lib().dugks_prof_query(self.h, int(kernel), byref(ms), byref(cnt)), "dugks_prof_query")
+        return ms.value, cnt.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            for inst in self.instances:
+                inst.h = None
+            lib().dugks_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
