@@ -143,12 +143,25 @@ int dugks_set_tau(dugks_t *h, const double *tau, int mem);
  * density of the current state is not finite anywhere. */
 int dugks_sync(dugks_t *h);
 
-/* Gradient of loss = sum_j dL_drho_j rho_j(T) + dL_du_j . u_j(T) after
- * nsteps steps from the physical initial state f0, with respect to f0
- * ([q][cell]) and the per-cell tau field ([cell]).  The forward pass is
- * recomputed from f0 with a checkpoint every ckpt_every steps.  Periodic,
- * uniform grids only (else DUGKS_ENOTSUP).  dL_drho may be NULL (zero);
- * dL_du is [2][cell]; outputs are caller-owned; dL_dtau may be NULL. */
+/* Discrete adjoint (not part of the paper's method): the exact gradient of
+ * the discrete map of nsteps steps (steps (1)-(4), eq. feqIntD3rdHat2_DS,
+ * preceded by the f -> fhat map) for
+ *     L = sum_j dL_drho_j rho_j(T) + dL_du_j . u_j(T)
+ * (rho, u: moments of the state as dugks_moments returns them), with respect
+ * to the physical initial state f0 ([q][cell]) and the per-cell relaxation
+ * time ([cell]; for a handle with a uniform tau the per-cell sensitivity is
+ * returned, whose sum is dL/dtau0).  dL_du is [2][cell] (x then y);
+ * dL_drho and dL_dtau may be NULL.  All pointers are in the memory named by
+ * mem; outputs are caller-owned.
+ * The forward pass is run from f0 keeping the state every ckpt_every steps;
+ * the reverse sweep recomputes each segment from its checkpoint, so device
+ * memory grows as (nsteps/ckpt_every + ckpt_every) states plus about 14
+ * double arrays of nq*nx*ny, allocated for the call and released before it
+ * returns.  The adjoint arithmetic is double for both precisions (for
+ * DUGKS_FP32_DELTA it linearises around the FP32 trajectory).  No atomics:
+ * results are bitwise reproducible.  The handle's state is left unchanged.
+ * Periodic uniform grids only (else DUGKS_ENOTSUP); batch handles:
+ * DUGKS_ENOTSUP; nsteps < 0 or ckpt_every < 1: DUGKS_EINVAL. */
 int dugks_backward(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
                    const double *dL_drho, const double *dL_du,
                    double *dL_df0, double *dL_dtau, int mem);

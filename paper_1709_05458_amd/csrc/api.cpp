@@ -1054,13 +1054,180 @@ static int batch_step(dugks_t *h, int nsteps)
     return DUGKS_OK;
 }
 
+// one stage of one step from explicit buffers (backward recomputation)
+static int stage_a_from(dugks *h, const void *X)
+{
+    if (h->lat) {
+        HIPCHECK(launch_stage(0, h->lat, h->delta, h->p, h->h1, X, nullptr, h->G, h->coefA, h->stream));
+    } else {
+        HIPCHECK(launch_state_moments(h->p, h->delta, X, h->mom_state, h->stream));
+        LQStage a{X, nullptr, h->G, h->mom_state, nullptr, h->face_part, h->face_mom,
+                  h->cell_part, h->mom_G, h->h1, 0};
+        HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
+    }
+    return DUGKS_OK;
+}
+
+static int step_from(dugks *h, const void *X, void *Y)
+{
+    int rc = stage_a_from(h, X);
+    if (rc) return rc;
+    if (h->lat) {
+        HIPCHECK(launch_stage(1, h->lat, h->delta, h->p, h->h2, h->G, X, Y, h->coefC, h->stream));
+    } else {
+        LQStage a{h->G, X, Y, h->mom_G, h->mom_state, h->face_part, h->face_mom,
+                  h->cell_part, h->mom_state, h->h2, 1};
+        HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
+    }
+    return DUGKS_OK;
+}
+
+// device workspace of one backward call, released (after the stream drains)
+// when the call returns
+struct Workspace {
+    hipStream_t s = nullptr;
+    std::vector<void *> bufs;
+    ~Workspace()
+    {
+        (void)hipStreamSynchronize(s);
+        for (void *b : bufs) (void)hipFree(b);
+    }
+    int raw(void **p, size_t bytes)
+    {
+        hipError_t e = hipMalloc(p, bytes ? bytes : 8);
+        if (e != hipSuccess) return fail(DUGKS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        bufs.push_back(*p);
+        return DUGKS_OK;
+    }
+    int get(double **p, size_t count)
+    {
+        void *v = nullptr;
+        int rc = raw(&v, count * sizeof(double));
+        *p = (double *)v;
+        return rc;
+    }
+};
+
 int dugks_backward(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
                    const double *dL_drho, const double *dL_du, double *dL_df0, double *dL_dtau,
                    int mem)
 {
-    (void)h; (void)f0; (void)nsteps; (void)ckpt_every; (void)dL_drho; (void)dL_du;
-    (void)dL_df0; (void)dL_dtau; (void)mem;
-    return fail(DUGKS_ENOTSUP, "adjoint not built yet");
+    if (!h || !f0 || !dL_du || !dL_df0 || nsteps < 0 || ckpt_every < 1)
+        return fail(DUGKS_EINVAL, "bad arguments");
+    if (h->batch) return fail(DUGKS_ENOTSUP, "backward of a batch handle");
+    const SweepParams &p = h->p;
+    if (!p.perx || !p.pery || !p.uniform)
+        return fail(DUGKS_ENOTSUP, "the adjoint supports periodic uniform grids only");
+    const long long n = p.ncell;
+    const int nq = p.nq;
+    const size_t nqn = (size_t)nq * n;
+    int rc;
+    Staged sf0, srho, su, sdf, sdt;
+    if ((rc = stage_in(f0, nqn, mem, sf0, h->stream)) || (rc = stage_in(dL_du, 2 * n, mem, su, h->stream)))
+        return rc;
+    if (dL_drho && (rc = stage_in(dL_drho, n, mem, srho, h->stream))) return rc;
+    if ((rc = stage_out(h, dL_df0, nqn, mem, sdf))) return rc;
+    if (dL_dtau && (rc = stage_out(h, dL_dtau, n, mem, sdt))) return rc;
+
+    Workspace ws;
+    ws.s = h->stream;
+    const int k = std::min(ckpt_every, std::max(nsteps, 1));
+    const int nseg = (nsteps + k - 1) / k;
+    std::vector<void *> ck(nseg + 1), seg(k);
+    for (auto &b : ck)
+        if ((rc = ws.raw(&b, h->elem * nqn))) return rc;
+    for (int t = 1; t < k; t++)
+        if ((rc = ws.raw(&seg[t], h->elem * nqn))) return rc;
+    double *fh_d, *B, *M, *G_d, *B2, *M2, *lam_fbar, *dtf, *lamLs, *lamB, *lamF, *lam[2], *dtau, *tau, *cA,
+        *cC;
+    if ((rc = ws.get(&fh_d, nqn)) || (rc = ws.get(&B, nqn)) || (rc = ws.get(&M, 3 * n)) ||
+        (rc = ws.get(&G_d, nqn)) || (rc = ws.get(&B2, nqn)) || (rc = ws.get(&M2, 3 * n)) ||
+        (rc = ws.get(&lam_fbar, 2 * nqn)) || (rc = ws.get(&dtf, 2 * n)) || (rc = ws.get(&lamLs, nqn)) ||
+        (rc = ws.get(&lamB, nqn)) || (rc = ws.get(&lamF, nqn)) || (rc = ws.get(&lam[0], nqn)) ||
+        (rc = ws.get(&lam[1], nqn)) || (rc = ws.get(&dtau, n)) || (rc = ws.get(&cA, 24 * (size_t)nq)) ||
+        (rc = ws.get(&cC, 24 * (size_t)nq)))
+        return rc;
+    if (p.tau_field) {
+        tau = const_cast<double *>(p.tau);
+    } else {
+        if ((rc = ws.get(&tau, n))) return rc;
+        std::vector<double> t0(n, p.tau0);
+        HIPCHECK(hipMemcpyAsync(tau, t0.data(), sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+        HIPCHECK(hipStreamSynchronize(h->stream));
+    }
+    {
+        // interface window weights in double for both stages (the forward
+        // kernels of FP32 storage hold them in float)
+        std::vector<double> xi(2 * (size_t)nq);
+        HIPCHECK(hipMemcpy(xi.data(), p.xi, sizeof(double) * nq, hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(xi.data() + nq, p.eta, sizeof(double) * nq, hipMemcpyDeviceToHost));
+        const double dx = 1.0 / p.inv_dx, dy = 1.0 / p.inv_dy;
+        std::vector<double> a = fast_coefs(xi.data(), nq, dx, dy, h->h1, p.kappa);
+        std::vector<double> c = fast_coefs(xi.data(), nq, dx, dy, h->h2, p.kappa);
+        HIPCHECK(hipMemcpyAsync(cA, a.data(), sizeof(double) * a.size(), hipMemcpyHostToDevice, h->stream));
+        HIPCHECK(hipMemcpyAsync(cC, c.data(), sizeof(double) * c.size(), hipMemcpyHostToDevice, h->stream));
+        HIPCHECK(hipStreamSynchronize(h->stream));
+    }
+    AdjArgs a{};
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nq = nq;
+    a.n = n;
+    a.dt = p.dt;
+    a.RT = p.RT;
+    a.iRT = p.iRT;
+    a.idx = p.inv_dx;
+    a.idy = p.inv_dy;
+    a.xi = p.xi;
+    a.eta = p.eta;
+    a.w = p.w;
+    a.tau = tau;
+    a.cA = cA;
+    a.cC = cC;
+    a.h1 = h->h1;
+    a.h2 = h->h2;
+
+    // forward pass from f0, keeping the state at every k-th step and the last
+    HIPCHECK(launch_set_state(p, h->delta, sf0.dev, ck[0], h->stream));
+    for (int i = 0; i < nseg; i++) {
+        const int len = std::min(k, nsteps - i * k);
+        const void *X = ck[i];
+        for (int t = 0; t < len; t++) {
+            void *Y = t == len - 1 ? ck[i + 1] : seg[t + 1];
+            if ((rc = step_from(h, X, Y))) return rc;
+            X = Y;
+        }
+    }
+    // seed from the final state
+    HIPCHECK(hipMemsetAsync(dtau, 0, sizeof(double) * n, h->stream));
+    HIPCHECK(adj_launch_prep(a, h->delta, p.rho0, ck[nseg], ck[nseg], fh_d, B, M, G_d, B2, M2, h->stream));
+    HIPCHECK(adj_launch_seed(a, fh_d, dL_drho ? srho.dev : nullptr, su.dev, lam[0], h->stream));
+    int cur = 0;
+    // reverse sweep, one checkpoint segment at a time
+    for (int i = nseg - 1; i >= 0; i--) {
+        const int len = std::min(k, nsteps - i * k);
+        const void *X = ck[i];
+        for (int t = 0; t + 1 < len; t++) {
+            if ((rc = step_from(h, X, seg[t + 1]))) return rc;
+            X = seg[t + 1];
+        }
+        for (int t = len - 1; t >= 0; t--) {
+            const void *Xt = t == 0 ? ck[i] : seg[t];
+            if ((rc = stage_a_from(h, Xt))) return rc;
+            HIPCHECK(adj_launch_prep(a, h->delta, p.rho0, Xt, h->G, fh_d, B, M, G_d, B2, M2, h->stream));
+            HIPCHECK(adj_launch_step(a, lam[cur], lam[1 - cur], fh_d, B, M, G_d, B2, M2, lam_fbar, dtf, lamLs,
+                                     lamB, lamF, dtau, h->stream));
+            cur = 1 - cur;
+        }
+    }
+    HIPCHECK(adj_launch_init(a, sf0.dev, lam[cur], sdf.dev, dtau, h->stream));
+    if (dL_dtau) HIPCHECK(hipMemcpyAsync(sdt.dev, dtau, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+    // the any-size kernels keep the moments of the current state in mom_state
+    if (!h->lat) HIPCHECK(launch_state_moments(p, h->delta, h->state[h->cur], h->mom_state, h->stream));
+    if ((rc = finish_out(h, dL_df0, nqn, mem, sdf))) return rc;
+    if (dL_dtau && (rc = finish_out(h, dL_dtau, n, mem, sdt))) return rc;
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return DUGKS_OK;
 }
 
 }  // extern "C"

@@ -126,4 +126,29 @@ hipError_t launch_init_eq(const SweepParams &p, bool delta, const double *rho, c
 hipError_t launch_moments(const SweepParams &p, bool delta, const void *state, double *rho,
                           double *ux, double *uy, int *bad, hipStream_t s);
 
+// Discrete adjoint of one step (adjoint.hip): periodic uniform grids, double.
+struct AdjArgs {
+    int nx, ny, nq;
+    long long n;
+    double dt, RT, iRT, idx, idy;
+    const double *xi, *eta, *w;
+    const double *tau;       // [cell]
+    const double *cA, *cC;   // [q][24] interface window weights of stage A / C
+    double h1, h2;
+};
+// Primal intermediates of a step from fhat and the stage A output G (storage
+// format): fhat, B and moments at t_n; G, B' and moments at t'.
+hipError_t adj_launch_prep(const AdjArgs &a, bool delta, double rho0, const void *fhat, const void *G,
+                           double *fh_d, double *B, double *M, double *G_d, double *B2, double *M2,
+                           hipStream_t s);
+// lambda_in = (d out / d fhat)^T lambda_out, dtau += (d out / d tau)^T lambda_out.
+hipError_t adj_launch_step(const AdjArgs &a, const double *lam_out, double *lam_in, const double *fh_d,
+                           const double *B, const double *M, const double *G_d, const double *B2,
+                           const double *M2, double *lam_fbar, double *dtau_face, double *lamLs,
+                           double *lamB, double *lamF, double *dtau, hipStream_t s);
+hipError_t adj_launch_seed(const AdjArgs &a, const double *fh_d, const double *dL_drho, const double *dL_du,
+                           double *lam, hipStream_t s);
+hipError_t adj_launch_init(const AdjArgs &a, const double *f0, const double *lam, double *dL_df0,
+                           double *dtau, hipStream_t s);
+
 }  // namespace dk

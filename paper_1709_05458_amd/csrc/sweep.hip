@@ -336,7 +336,7 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
     const int i = i0 + lx, j = j0 + ly;
     const bool valid = (i < p.nx) && (j < p.ny);
     const long long n = p.ncell;
-    const double dt = p.dt, RT = p.RT, cl = p.clat;
+    const double dt = p.dt, cl = p.clat;
     const double *__restrict__ W = p.w;
     const double *__restrict__ WM = p.wmom;
     const long long ocell = (long long)j * p.nx + i;

@@ -163,7 +163,7 @@ class Solver:
 
     def __init__(self, case, precision: int = FP64, taylor_quad: float = 1.0, stream=None,
                  tile=None, allow_defect: bool = False, tau=None, force_generic: bool = False,
-                 _borrowed=None):
+                 tau_field: bool = False, _borrowed=None):
         g, vs = case.grid, case.vs
         self.case = case
         self.nx, self.ny, self.nq = g.nx, g.ny, vs.nq
@@ -184,12 +184,12 @@ class Solver:
         d.RT, d.dt = vs.RT, case.dt
         tau = case.tau if tau is None else tau
         tau = np.asarray(tau, dtype=np.float64)
-        if tau.ndim == 0 or np.ptp(tau) == 0.0:
+        if not tau_field and (tau.ndim == 0 or np.ptp(tau) == 0.0):
             d.tau = POINTER(c_double)()
             d.tau0 = float(tau.reshape(-1)[0])
             self.tau_field = False
         else:
-            t = np.ascontiguousarray(tau.reshape(-1))
+            t = np.ascontiguousarray(np.broadcast_to(tau, (g.ny, g.nx)).reshape(-1))
             self._keep.append(t)
             d.tau = _dptr(t)
             d.tau0 = float(t.mean())
@@ -287,6 +287,33 @@ class Solver:
     def get_fhat(self, out=None):
         return self._dist(lib().dugks_get_fhat, out)
 
+    # -- adjoint -------------------------------------------------------------
+    def backward(self, f0, nsteps: int, ckpt_every: int = 25, dL_drho=None, dL_du=None,
+                 want_tau: bool = True):
+        """Gradients (dL/df0 [q][y][x], dL/dtau [y][x] or None) of
+        L = sum dL_drho * rho(T) + dL_du . u(T) after nsteps steps from the
+        physical state f0 (dugks_backward).  Torch device tensors in, torch
+        device tensors out; otherwise numpy."""
+        if dL_du is None:
+            raise ValueError("dL_du is required (zeros for a density-only loss)")
+        if _is_torch(f0) and f0.is_cuda:
+            import torch
+            gf = torch.empty(self.nq, self.ny, self.nx, dtype=torch.float64, device=f0.device)
+            gt = torch.empty(self.ny, self.nx, dtype=torch.float64, device=f0.device) if want_tau else None
+        else:
+            gf = np.empty((self.nq, self.ny, self.nx))
+            gt = np.empty((self.ny, self.nx)) if want_tau else None
+        pf, mem, k0 = _ptr_mem(f0)
+        pu, mu, k1 = _ptr_mem(dL_du)
+        pr, mr, k2 = _ptr_mem(dL_drho) if dL_drho is not None else (None, mem, None)
+        pg, mg, k3 = _ptr_mem(gf)
+        pt, mt, k4 = _ptr_mem(gt) if gt is not None else (None, mem, None)
+        if len({mem, mu, mr, mg, mt}) != 1:
+            raise ValueError("all arrays of backward must live in the same memory")
+        check(lib().dugks_backward(self.h, pf, int(nsteps), int(ckpt_every), pr, pu, pg, pt, mem),
+              "dugks_backward")
+        return gf, gt
+
     # -- timing --------------------------------------------------------------
     def prof_begin(self, max_launches: int):
         check(lib().dugks_prof_begin(self.h, int(max_launches)), "dugks_prof_begin")
@@ -299,6 +326,58 @@ class Solver:
 
     def prof_end(self):
         check(lib().dugks_prof_end(self.h), "dugks_prof_end")
+
+
+def _run_function():
+    import torch
+
+    class DugksRun(torch.autograd.Function):
+        """(rho(T), u(T)) after `nsteps` steps from the physical initial state
+        f0 [q][y][x] with the relaxation-time field tau [y][x]; the backward
+        pass is the library's discrete adjoint (dugks_backward), with a
+        checkpoint every `ckpt_every` steps."""
+
+        @staticmethod
+        def forward(ctx, f0, tau, solver, nsteps, ckpt_every):
+            f0 = f0.detach().contiguous()
+            if tau is not None:
+                tau = tau.detach().contiguous()
+                solver.set_tau(tau)
+            solver.set_state(f0)
+            solver.step(nsteps)
+            rho = torch.empty(solver.ny, solver.nx, dtype=torch.float64, device=f0.device)
+            u = torch.empty(2, solver.ny, solver.nx, dtype=torch.float64, device=f0.device)
+            solver.moments(out=(rho, u[0], u[1]))
+            ctx.save_for_backward(f0, tau if tau is not None else torch.empty(0))
+            ctx.solver, ctx.nsteps, ctx.ckpt, ctx.has_tau = solver, nsteps, ckpt_every, tau is not None
+            return rho, u
+
+        @staticmethod
+        def backward(ctx, g_rho, g_u):
+            f0, tau = ctx.saved_tensors
+            s = ctx.solver
+            if ctx.has_tau:
+                s.set_tau(tau)
+            if g_u is None:
+                g_u = torch.zeros(2, s.ny, s.nx, dtype=torch.float64, device=f0.device)
+            gr = None if g_rho is None else g_rho.contiguous()
+            gf, gt = s.backward(f0, ctx.nsteps, ctx.ckpt, gr, g_u.contiguous(),
+                                want_tau=ctx.has_tau and ctx.needs_input_grad[1])
+            return gf, gt, None, None, None
+
+    return DugksRun
+
+
+_RUN = None
+
+
+def run(f0, tau, solver: Solver, nsteps: int, ckpt_every: int = 25):
+    """Differentiable (rho(T), u(T)) of a torch float64 f0 [q][y][x] and tau
+    [y][x] (or None): see DugksRun."""
+    global _RUN
+    if _RUN is None:
+        _RUN = _run_function()
+    return _RUN.apply(f0, tau, solver, int(nsteps), int(ckpt_every))
 
 
 class BatchSolver:
