@@ -10,7 +10,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdugks.so")
-SOURCES = ["sweep.hip", "sweep_large.hip", "aux.hip", "adjoint.hip", "api.cpp"]
+SOURCES = ["sweep.hip", "sweep_fast.hip", "sweep_large.hip", "aux.hip", "adjoint.hip", "api.cpp"]
 ARCH = "gfx950"
 # -packed-fp32-ops: no packed FP32 instructions are generated.
 FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

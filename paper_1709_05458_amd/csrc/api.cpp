@@ -12,12 +12,14 @@
 
 #include "../../include/dugks.h"
 #include "dugks_internal.h"
+#include "lattices.h"
 
 using namespace dk;
 
 struct dugks {
     SweepParams p{};
     int lat = 0;          // 9, 37 (compile-time lattices) or 0 (generic)
+    bool fast_ct = false; // fast-kind tiles run the compile-time-shape kernels
     bool delta = false;
     hipStream_t stream = nullptr;
     size_t elem = 8;      // bytes per stored element
@@ -49,12 +51,18 @@ struct dugks::Batch {
     SweepParams *d_params = nullptr;
     StageIO *d_io = nullptr;        // [parity][stage][instance]
     LQStage *d_lq = nullptr;        // [parity][stage][instance]
+    struct Shape {                  // fast-kind tiles of one compiled tile shape
+        int tx = 0, ty = 0;
+        int4 *work = nullptr;
+        int n = 0;
+    };
     struct Group {                  // one lattice kind
         int lat = 0;
         int nthreads = 0;
         size_t smem = 0;
-        int4 *fast = nullptr, *gen = nullptr;
+        int4 *fast = nullptr, *gen = nullptr;   // fast: tiles of shapes without a compiled kernel
         int nfast = 0, ngen = 0;
+        std::vector<Shape> shapes;
     };
     std::vector<Group> groups;
     int4 *lq_tiles = nullptr, *lq_faces = nullptr, *lq_cells = nullptr;
@@ -243,6 +251,34 @@ static bool is_uniform(const double *f, int n)
     for (int i = 0; i < n; i++)
         if (std::fabs((f[i + 1] - f[i]) - d0) > 1e-12 * std::fabs(d0)) return false;
     return true;
+}
+
+// The dynamic-LDS limit is a per-kernel attribute: only ever raise it.
+static int raise_fast_smem(int lat, bool delta, int tx, int ty, size_t smem)
+{
+    static size_t raised[2][2][8] = {};
+    const int k = fast_tile_index(tx, ty);
+    if (k < 0 || k >= 8) return fail(DUGKS_EINVAL, "no compiled kernel for this tile");
+    size_t &mx = raised[lat == 9 ? 0 : 1][delta ? 1 : 0][k];
+    if (smem > mx) {
+        hipError_t e = set_fast_smem(lat, delta, tx, ty, smem);
+        if (e != hipSuccess) return fail(DUGKS_EDEVICE, std::string("LDS size: ") + hipGetErrorString(e));
+        mx = smem;
+    }
+    return DUGKS_OK;
+}
+
+// one stage of a lattice instance: fast-kind tiles by the compile-time-shape
+// kernel when the tile is one of the compiled shapes, the rest by the general one
+static hipError_t lattice_stage(const dugks *h, int stage, const void *X, const void *F, void *out)
+{
+    const void *coef = stage == 0 ? h->coefA : h->coefC;
+    const double hs = stage == 0 ? h->h1 : h->h2;
+    if (!h->fast_ct) return launch_stage(stage, h->lat, h->delta, h->p, hs, X, F, out, coef, h->stream, 3);
+    hipError_t e = hipSuccess;
+    if (h->p.uniform) e = launch_stage_fast(stage, h->lat, h->delta, h->p, hs, X, F, out, coef, h->stream);
+    if (e != hipSuccess) return e;
+    return launch_stage(stage, h->lat, h->delta, h->p, hs, X, F, out, coef, h->stream, 2);
 }
 
 // ---------------------------------------------------------------------------
@@ -458,8 +494,10 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
         p.lq_nchunk = (nq + p.lq_chunk - 1) / p.lq_chunk;
         p.lq_qs = 8;
     }
+    // lattice kernels: one plane of the tile and its halo per velocity, plus one
+    // spare element per plane (compile-time-shape kernels)
     const size_t smem = h->lat == 0 ? lq_smem_bytes(p, h->delta)
-                                    : h->elem * nq * (size_t)(lx + 4) * (ly + 4);
+                                    : h->elem * nq * ((size_t)(lx + 4) * (ly + 4) + 1);
     if (smem > 160 * 1024) {
         delete h;
         return fail(DUGKS_EINVAL, "tile too large for LDS");
@@ -476,6 +514,28 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
         if (e != hipSuccess) {
             delete h;
             return fail(DUGKS_EDEVICE, std::string("LDS size: ") + hipGetErrorString(e));
+        }
+    }
+
+    p.ncell_f = p.ncell_o = ncell;
+    if (h->lat && fast_tile_index(lx, ly) >= 0) {
+        // the compile-time-shape kernels take the weights per velocity shell and
+        // address planes with 32-bit byte offsets
+        bool ok = ncell * (long long)h->elem < (1LL << 32);
+        for (int q = 0; q < nq && ok; q++) {
+            const int sh = h->lat == 9 ? LatD2Q9::shell(q) : LatD2Q37::shell(q);
+            double &w1 = p.wtab[sh][1];
+            if (w1 == 0.0) w1 = d->w[q];
+            else ok = std::fabs(d->w[q] - w1) <= 1e-14 * std::fabs(w1);
+        }
+        for (int sh = 0; sh < 8; sh++)
+            for (int m = 0; m < 4; m++) p.wtab[sh][m] = m * p.wtab[sh][1];
+        if (ok) {
+            if ((rc = raise_fast_smem(h->lat, h->delta, lx, ly, smem))) {
+                delete h;
+                return rc;
+            }
+            h->fast_ct = true;
         }
     }
 
@@ -687,7 +747,7 @@ int dugks_step(dugks_t *h, int nsteps)
         int rc;
         if ((rc = record(h, KC_STAGE_A, true))) return rc;
         if (h->lat) {
-            HIPCHECK(launch_stage(0, h->lat, h->delta, h->p, h->h1, X, nullptr, h->G, h->coefA, h->stream));
+            HIPCHECK(lattice_stage(h, 0, X, nullptr, h->G));
         } else {
             LQStage a{X, nullptr, h->G, h->mom_state, nullptr, h->face_part, h->face_mom,
                       h->cell_part, h->mom_G, h->h1, 0};
@@ -696,7 +756,7 @@ int dugks_step(dugks_t *h, int nsteps)
         if ((rc = record(h, KC_STAGE_A, false))) return rc;
         if ((rc = record(h, KC_STAGE_C, true))) return rc;
         if (h->lat) {
-            HIPCHECK(launch_stage(1, h->lat, h->delta, h->p, h->h2, h->G, X, Y, h->coefC, h->stream));
+            HIPCHECK(lattice_stage(h, 1, h->G, X, Y));
         } else {
             // the moments of fhat(t_n) are read by the update and overwritten by
             // the cell reduction that follows it on the same stream
@@ -907,6 +967,8 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
         dugks::Batch::Group g;
         g.lat = lat;
         std::vector<int4> fast, gen;
+        std::vector<std::vector<int4>> by_shape(8);
+        std::vector<std::pair<int, int>> shape_of(8, {0, 0});
         for (int k = 0; k < n; k++) {
             dugks *c = b->inst[k];
             if (c->lat != lat) continue;
@@ -917,14 +979,20 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
                 dugks_destroy(h);
                 return fail(DUGKS_EINVAL, "instances of one lattice in a batch need tiles of equal size");
             }
-            g.smem = std::max(g.smem, c->elem * (size_t)p.nq * (p.tile_x + 4) * (p.tile_y + 4));
+            g.smem = std::max(g.smem, c->elem * (size_t)p.nq * ((size_t)(p.tile_x + 4) * (p.tile_y + 4) + 1));
             const int gx = (p.nx + p.tile_x - 1) / p.tile_x, gy = (p.ny + p.tile_y - 1) / p.tile_y;
             for (int ty = 0; ty < gy; ty++)
                 for (int tx = 0; tx < gx; tx++) {
                     const int i0 = tx * p.tile_x, j0 = ty * p.tile_y;
                     const bool isfast = p.uniform && (p.perx || (i0 >= 2 && i0 + p.tile_x <= p.nx - 2)) &&
                                         (p.pery || (j0 >= 2 && j0 + p.tile_y <= p.ny - 2));
-                    (isfast ? fast : gen).push_back(make_int4(k, tx, ty, 0));
+                    const int si = c->fast_ct ? fast_tile_index(p.tile_x, p.tile_y) : -1;
+                    if (isfast && si >= 0) {
+                        by_shape[si].push_back(make_int4(k, tx, ty, 0));
+                        shape_of[si] = {p.tile_x, p.tile_y};
+                    } else {
+                        (isfast ? fast : gen).push_back(make_int4(k, tx, ty, 0));
+                    }
                 }
         }
         if (g.nthreads == 0) continue;
@@ -933,6 +1001,19 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
         if ((rc = batch_upload(b, fast, &g.fast)) || (rc = batch_upload(b, gen, &g.gen))) {
             dugks_destroy(h);
             return rc;
+        }
+        for (int si = 0; si < 8; si++) {
+            if (by_shape[si].empty()) continue;
+            dugks::Batch::Shape sh;
+            sh.tx = shape_of[si].first;
+            sh.ty = shape_of[si].second;
+            sh.n = (int)by_shape[si].size();
+            if ((rc = raise_fast_smem(lat, b->delta, sh.tx, sh.ty, g.smem)) ||
+                (rc = batch_upload(b, by_shape[si], &sh.work))) {
+                dugks_destroy(h);
+                return rc;
+            }
+            g.shapes.push_back(sh);
         }
         b->groups.push_back(g);
     }
@@ -997,9 +1078,13 @@ static int batch_enqueue_step(dugks *h, int par)
     const int n = (int)b->inst.size();
     for (int stage = 0; stage < 2; stage++) {
         const StageIO *io = b->d_io + (size_t)(par * 2 + stage) * n;
-        for (const auto &g : b->groups)
+        for (const auto &g : b->groups) {
+            for (const auto &sh : g.shapes)
+                HIPCHECK(launch_stage_fast_batched(stage, g.lat, b->delta, sh.tx, sh.ty, b->d_params, io, sh.work,
+                                                   sh.n, g.smem, h->stream));
             HIPCHECK(launch_stage_batched(stage, g.lat, b->delta, b->d_params, io, g.fast, g.nfast, g.gen,
                                           g.ngen, g.nthreads, g.smem, h->stream));
+        }
         if (b->nlq_tiles)
             HIPCHECK(launch_lq_stage_batched(b->delta, b->d_params, b->d_lq + (size_t)(par * 2 + stage) * n,
                                              b->lq_tiles, b->nlq_tiles, b->lq_faces, b->nlq_faces,
@@ -1058,7 +1143,7 @@ static int batch_step(dugks_t *h, int nsteps)
 static int stage_a_from(dugks *h, const void *X)
 {
     if (h->lat) {
-        HIPCHECK(launch_stage(0, h->lat, h->delta, h->p, h->h1, X, nullptr, h->G, h->coefA, h->stream));
+        HIPCHECK(lattice_stage(h, 0, X, nullptr, h->G));
     } else {
         HIPCHECK(launch_state_moments(h->p, h->delta, X, h->mom_state, h->stream));
         LQStage a{X, nullptr, h->G, h->mom_state, nullptr, h->face_part, h->face_mom,
@@ -1073,7 +1158,7 @@ static int step_from(dugks *h, const void *X, void *Y)
     int rc = stage_a_from(h, X);
     if (rc) return rc;
     if (h->lat) {
-        HIPCHECK(launch_stage(1, h->lat, h->delta, h->p, h->h2, h->G, X, Y, h->coefC, h->stream));
+        HIPCHECK(lattice_stage(h, 1, h->G, X, Y));
     } else {
         LQStage a{h->G, X, Y, h->mom_G, h->mom_state, h->face_part, h->face_mom,
                   h->cell_part, h->mom_state, h->h2, 1};

@@ -49,6 +49,13 @@ struct SweepParams {
     // velocity set (device)
     const double *xi, *eta, *w;
     const double *wmom;      // [nq][3]: moment weights (w, w ex, w ey) in lattice units
+    // lattices: weight of each velocity shell times 1, 2, 3 (wtab[shell][m] =
+    // m w_shell), read from the kernel arguments by the fast lattice kernels
+    double wtab[8][4];
+    // = ncell; separate copies keep the compiler from sharing per-velocity
+    // plane offsets between the load, update and store phases of a kernel
+    // (dozens of long-lived scalar registers)
+    long long ncell_f, ncell_o;
     const int *opp;
     // walls
     int bc[4];
@@ -94,10 +101,20 @@ enum KernelClass { KC_STAGE_A = 0, KC_STAGE_C = 1, KC_AUX = 2, KC_COUNT = 3 };
 
 // Host launchers (defined in sweep.hip).  `lat`: 0 generic, 9 D2Q9, 37 D2Q37.
 // `delta`: FP32-delta storage (float) else FP64 storage (double).
+// parts: 1 = tiles of the fast kind, 2 = the others, 3 = all.
 hipError_t launch_stage(int stage, int lat, bool delta, const SweepParams &p, double h,
                         const void *X, const void *F, void *out, const void *coef,
-                        hipStream_t s);
+                        hipStream_t s, int parts = 3);
 hipError_t set_stage_smem(int lat, bool delta, size_t bytes);
+// Fast-kind tiles with a compile-time tile shape (sweep_fast.hip): index of
+// the shape among the compiled ones, or -1.
+int fast_tile_index(int tx, int ty);
+hipError_t set_fast_smem(int lat, bool delta, int tx, int ty, size_t bytes);
+hipError_t launch_stage_fast(int stage, int lat, bool delta, const SweepParams &p, double h, const void *X,
+                             const void *F, void *out, const void *coef, hipStream_t s);
+hipError_t launch_stage_fast_batched(int stage, int lat, bool delta, int tx, int ty, const SweepParams *P,
+                                     const StageIO *io, const int4 *work, int nwork, size_t smem,
+                                     hipStream_t s);
 // Many instances in one launch per tile kind: work items (instance, tile x, tile y, 0).
 hipError_t launch_stage_batched(int stage, int lat, bool delta, const SweepParams *P, const StageIO *io,
                                 const int4 *work_fast, int nfast, const int4 *work_gen, int ngen,

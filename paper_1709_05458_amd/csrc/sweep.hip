@@ -17,44 +17,9 @@
 // of the recovered interface distribution (eq. recover2f) is added once the
 // interface moments are complete.
 #include "dugks_internal.h"
+#include "lattices.h"
 
 #include <utility>
-
-namespace dk {
-
-// ---------------------------------------------------------------------------
-// Lattices: velocity q = clat * (ex(q), ey(q)).
-// ---------------------------------------------------------------------------
-struct LatD2Q9 {
-    static constexpr int Q = 9;
-    static constexpr __host__ __device__ int ex(int q) { return q / 3 - 1; }
-    static constexpr __host__ __device__ int ey(int q) { return q % 3 - 1; }
-    static constexpr __host__ __device__ int opp(int q) { return 8 - q; }
-};
-
-struct LatD2Q37 {
-    static constexpr int Q = 37;
-    static constexpr __host__ __device__ int ex(int q)
-    {
-        constexpr int t[37] = {0, -1, 0, 0, 1, -1, -1, 1, 1, -2, 0, 0, 2, -2, -2, -1, -1, 1, 1,
-                               2, 2, -2, -2, 2, 2, -3, 0, 0, 3, -3, -3, -1, -1, 1, 1, 3, 3};
-        return t[q];
-    }
-    static constexpr __host__ __device__ int ey(int q)
-    {
-        constexpr int t[37] = {0, 0, -1, 1, 0, -1, 1, -1, 1, 0, -2, 2, 0, -1, 1, -2, 2, -2, 2,
-                               -1, 1, -2, 2, -2, 2, 0, -3, 3, 0, -1, 1, -3, 3, -3, 3, -1, 1};
-        return t[q];
-    }
-    static constexpr __host__ __device__ int opp(int q)
-    {
-        constexpr int t[37] = {0, 4, 3, 2, 1, 8, 7, 6, 5, 12, 11, 10, 9, 20, 19, 18, 17, 16, 15,
-                               14, 13, 24, 23, 22, 21, 28, 27, 26, 25, 36, 35, 34, 33, 32, 31, 30, 29};
-        return t[q];
-    }
-};
-
-}  // namespace dk
 
 #include "sweep_common.h"
 
@@ -292,29 +257,6 @@ __device__ __forceinline__ void moment_q(const S *v, const double *__restrict__ 
 // tiles (walls, one-sided stencils, non-uniform spacing).  Each instance
 // returns at once on the tiles of the other kind.
 // ---------------------------------------------------------------------------
-// Workgroups are dealt to the XCDs round-robin (block b runs on XCD b % nxcd).
-// Give every XCD a contiguous range of row-major tiles so that neighbouring
-// tiles, which read each other's halo, share that XCD's L2.
-__device__ __forceinline__ void tile_of_block(const SweepParams &p, int &tx, int &ty)
-{
-    const int gx = (p.nx + p.tile_x - 1) / p.tile_x;
-    const int gy = (p.ny + p.tile_y - 1) / p.tile_y;
-    const int nb = gx * gy;
-    const int b = blockIdx.x;
-    const int nx8 = p.nxcd;
-    const int per = nb / nx8, rem = nb % nx8;
-    const int x = b % nx8, slot = b / nx8;
-    const int t = x * per + (x < rem ? x : rem) + slot;
-    tx = t % gx;
-    ty = t / gx;
-}
-
-__device__ __forceinline__ bool tile_is_fast(const SweepParams &p, int i0, int j0, int TX, int TY)
-{
-    return p.uniform && (p.perx || (i0 >= 2 && i0 + TX <= p.nx - 2)) &&
-           (p.pery || (j0 >= 2 && j0 + TY <= p.ny - 2));
-}
-
 template <class Lat, class S, bool DELTA, int STAGE, bool GENERAL>
 __device__ __forceinline__ void
 sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
@@ -615,15 +557,15 @@ sweep_small_batched(const SweepParams *__restrict__ P, const StageIO *__restrict
 // ---------------------------------------------------------------------------
 template <class Lat, class S, bool DELTA, int STAGE>
 static hipError_t launch_t(const SweepParams &p, double h, const void *X, const void *F, void *out,
-                           const void *coef, hipStream_t s)
+                           const void *coef, hipStream_t s, int parts)
 {
     dim3 grid(((p.nx + p.tile_x - 1) / p.tile_x) * ((p.ny + p.tile_y - 1) / p.tile_y));
     dim3 block(p.tile_x * p.tile_y);
     size_t smem = sizeof(S) * Lat::Q * (size_t)(p.tile_x + 4) * (p.tile_y + 4);
     // tiles of the fast kind exist unless the grid is non-uniform; tiles of the
     // general kind exist unless the domain is uniform and fully periodic
-    const bool any_fast = p.uniform;
-    const bool any_general = !(p.uniform && p.perx && p.pery);
+    const bool any_fast = p.uniform && (parts & 1);
+    const bool any_general = !(p.uniform && p.perx && p.pery) && (parts & 2);
     if (any_fast)
         hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, false>), grid, block, smem, s, p, h,
                            (const S *)X, (const S *)F, (S *)out, (const S *)coef);
@@ -693,11 +635,11 @@ hipError_t set_stage_smem(int lat, bool delta, size_t bytes)
 }
 
 hipError_t launch_stage(int stage, int lat, bool delta, const SweepParams &p, double h,
-                        const void *X, const void *F, void *out, const void *coef, hipStream_t s)
+                        const void *X, const void *F, void *out, const void *coef, hipStream_t s, int parts)
 {
 #define DUGKS_L(LAT, S_, D_)                                                              \
-    return stage == 0 ? launch_t<LAT, S_, D_, 0>(p, h, X, F, out, coef, s)               \
-                      : launch_t<LAT, S_, D_, 1>(p, h, X, F, out, coef, s)
+    return stage == 0 ? launch_t<LAT, S_, D_, 0>(p, h, X, F, out, coef, s, parts)        \
+                      : launch_t<LAT, S_, D_, 1>(p, h, X, F, out, coef, s, parts)
     if (lat == 9) {
         if (delta) DUGKS_L(LatD2Q9, float, true);
         DUGKS_L(LatD2Q9, double, false);

@@ -165,4 +165,27 @@ __device__ __forceinline__ double expand_general(const SweepParams &p, const S *
 }
 
 
+// Workgroups are dealt to the XCDs round-robin (block b runs on XCD b % nxcd).
+// Give every XCD a contiguous range of row-major tiles so that neighbouring
+// tiles, which read each other's halo, share that XCD's L2.
+__device__ __forceinline__ void tile_of_block(const SweepParams &p, int &tx, int &ty)
+{
+    const int gx = (p.nx + p.tile_x - 1) / p.tile_x;
+    const int gy = (p.ny + p.tile_y - 1) / p.tile_y;
+    const int nb = gx * gy;
+    const int b = blockIdx.x;
+    const int nx8 = p.nxcd;
+    const int per = nb / nx8, rem = nb % nx8;
+    const int x = b % nx8, slot = b / nx8;
+    const int t = x * per + (x < rem ? x : rem) + slot;
+    tx = t % gx;
+    ty = t / gx;
+}
+
+__device__ __forceinline__ bool tile_is_fast(const SweepParams &p, int i0, int j0, int TX, int TY)
+{
+    return p.uniform && (p.perx || (i0 >= 2 && i0 + TX <= p.nx - 2)) &&
+           (p.pery || (j0 >= 2 && j0 + TY <= p.ny - 2));
+}
+
 }  // namespace dk
