@@ -486,13 +486,18 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     p.tile_x = lx;
     p.tile_y = ly;
     if (h->lat == 0) {
-        // chunks: enough workgroups to fill the chip, at least 16 velocities each
-        const long long ntile = (long long)((d->nx + lx - 1) / lx) * ((d->ny + ly - 1) / ly);
+        // ring tiles (one block covers (lx - 2) x (ly - 2) cells); chunks: enough
+        // workgroups to fill the chip, at least 16 velocities each
+        if (lx < 4 || ly < 4) {
+            delete h;
+            return fail(DUGKS_EINVAL, "any-size velocity sets need tiles of at least 4 x 4 threads");
+        }
+        const long long ntile = lq_ntile(p);
         int nch = (int)std::max(1LL, (2048 + ntile - 1) / ntile);
         nch = std::min(nch, std::max(1, nq / 16));
         p.lq_chunk = (nq + nch - 1) / nch;
         p.lq_nchunk = (nq + p.lq_chunk - 1) / p.lq_chunk;
-        p.lq_qs = 8;
+        p.lq_qs = 4;
     }
     // lattice kernels: one plane of the tile and its halo per velocity, plus one
     // spare element per plane (compile-time-shape kernels)
@@ -566,6 +571,26 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
             wm[3 * q + 2] = w0 * std::round(eta[q] / c);
         }
         UP(wm, p.wmom)
+    }
+    if (h->lat == 0) {
+        // any-size kernels: moment weights and monomials of every velocity
+        std::vector<double> lw(3 * (size_t)nq), md(9 * (size_t)nq);
+        std::vector<float> mf(9 * (size_t)nq);
+        for (int q = 0; q < nq; q++) {
+            const double m = h->delta ? d->w[q] : 1.0, x = xi[q], y = eta[q];
+            lw[3 * q] = m;
+            lw[3 * q + 1] = m * x;
+            lw[3 * q + 2] = m * y;
+            const double mono[9] = {x, y, x * x, x * y, y * y, x * x * x, x * x * y, x * y * y, y * y * y};
+            for (int k = 0; k < 9; k++) {
+                md[9 * q + k] = mono[k];
+                mf[9 * q + k] = (float)mono[k];
+            }
+        }
+        std::vector<int> sg(nq);
+        for (int q = 0; q < nq; q++)
+            sg[q] = (xi[q] > 0 ? 1 : 0) | (xi[q] < 0 ? 2 : 0) | (eta[q] > 0 ? 4 : 0) | (eta[q] < 0 ? 8 : 0);
+        UP(lw, p.lq_wm) UP(md, p.lq_mono_d) UP(mf, p.lq_mono_f) UP(sg, p.lq_sgn)
     }
     if (d->tau) {
         std::vector<double> vt(d->tau, d->tau + ncell);
@@ -1030,7 +1055,7 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
                 return fail(DUGKS_EINVAL, "any-size instances in a batch need tiles of equal size");
             }
             b->lq_smem = std::max(b->lq_smem, lq_smem_bytes(p, b->delta));
-            const int ntile = ((p.nx + p.tile_x - 1) / p.tile_x) * ((p.ny + p.tile_y - 1) / p.tile_y);
+            const int ntile = lq_ntile(p);
             for (int ch = 0; ch < p.lq_nchunk; ch++)
                 for (int t = 0; t < ntile; t++) tiles.push_back(make_int4(k, t, ch, 0));
             const long long nface = (long long)(p.nx + 1) * p.ny + (long long)p.nx * (p.ny + 1);

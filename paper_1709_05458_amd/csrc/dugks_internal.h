@@ -70,6 +70,10 @@ struct SweepParams {
     // large velocity sets: q split into lq_nchunk chunks of lq_chunk velocities,
     // streamed through LDS lq_qs planes at a time
     int lq_chunk, lq_nchunk, lq_qs;
+    const double *lq_wm;     // [nq][3] moment weights (m, m xi, m eta), m = w (FP32-delta) or 1
+    const float *lq_mono_f;  // [nq][9] xi, eta, xi^2, xi eta, eta^2, xi^3, xi^2 eta, xi eta^2, eta^3
+    const double *lq_mono_d;
+    const int *lq_sgn;       // [nq] bit 0: xi > 0, 1: xi < 0, 2: eta > 0, 3: eta < 0
 };
 
 // Per-stage arguments of the large-velocity-set kernels.
@@ -128,6 +132,12 @@ hipError_t launch_lq_stage_batched(bool delta, const SweepParams *P, const LQSta
 
 // Large velocity sets (sweep_large.hip).  part < 0: all four kernels of the stage.
 hipError_t launch_lq_stage(bool delta, const SweepParams &p, const LQStage &a, hipStream_t s, int part);
+// Ring tiles of the any-size kernels: a block of tile_x x tile_y threads
+// covers (tile_x - 2) x (tile_y - 2) cells.
+__host__ __device__ inline int lq_ntile(const SweepParams &p)
+{
+    return ((p.nx + p.tile_x - 3) / (p.tile_x - 2)) * ((p.ny + p.tile_y - 3) / (p.tile_y - 2));
+}
 hipError_t set_lq_smem(bool delta, size_t bytes);
 size_t lq_smem_bytes(const SweepParams &p, bool delta);
 hipError_t launch_state_moments(const SweepParams &p, bool delta, const void *state, double *mom,

@@ -16,6 +16,8 @@
 // diffuse boundaries (bounce-back needs the lattice kernels).
 #include "sweep_common.h"
 
+#include <algorithm>
+
 namespace dk {
 
 __device__ __forceinline__ long long xface_id(const SweepParams &p, int fi, int j)
@@ -49,69 +51,172 @@ __device__ __forceinline__ void stage_transform(const SweepParams &p, int stage,
     }
 }
 
-// E_q(moments) / s_q - r0 for runtime velocity (xq, yq), from EPoly coefficients
-// built with clat = 1.
-template <class S>
-__device__ __forceinline__ S eval_rt(const S *c, S xq, S yq)
+// Per-velocity tables read by every thread of a block at the same address.
+// They are not written while a stage runs; reading them through the constant
+// address space lets the compiler use scalar loads inside the loops over
+// velocities (which contain barriers).
+template <class T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+template <class T>
+__device__ __forceinline__ cptr<T> as_const(const T *p)
 {
-    S v = c[0];
-    v = fmaS(xq, c[1], v);
-    v = fmaS(yq, c[2], v);
-    v = fmaS(xq * xq, c[3], v);
-    v = fmaS(xq * yq, c[4], v);
-    v = fmaS(yq * yq, c[5], v);
-    return v;
+    return (cptr<T>)p;
 }
 
-// Shared memory of a large-Q block: QS planes of B over the halo tile, and per
-// halo cell the scaled equilibrium coefficients (6) and the transform weight.
 template <class S>
-struct LQShared {
-    S *planes;   // [QS][plane]
-    S *ecoef;    // [7][plane]
+__device__ __forceinline__ cptr<S> mono_table(const SweepParams &p);
+template <>
+__device__ __forceinline__ cptr<float> mono_table<float>(const SweepParams &p) { return as_const(p.lq_mono_f); }
+template <>
+__device__ __forceinline__ cptr<double> mono_table<double>(const SweepParams &p) { return as_const(p.lq_mono_d); }
+
+// Planes of B held in LDS at once (velocities per group).
+template <bool DELTA>
+constexpr int lq_group() { return DELTA ? 4 : 4; }
+
+// ---------------------------------------------------------------------------
+// Ring tiles.  A block of TX x TY threads covers the cells (i0-1 .. i0+TX-2) x
+// (j0-1 .. j0+TY-2): the (TX-2) x (TY-2) tile interior and a ring of one cell.
+// Every thread forms, per velocity, the derivatives of B at its own cell and
+// the interface values of the faces for which its cell is the upwind cell
+// (eq. flux_DS): the east face if xi > 0, the west face if xi < 0, half of
+// each if xi = 0 (the mean of both expansions), and likewise in y.  Each
+// interface value is thus formed once; the ring supplies the values of the
+// faces between the interior and the ring.  LDS holds B over the cells
+// (i0-2 .. i0+TX-1) x (j0-2 .. j0+TY-1), which covers the 3 x 3 stencil of
+// every thread's cell.
+// ---------------------------------------------------------------------------
+template <class S>
+struct RingCell {
+    int i, j;            // global cell (periodic wrap applied)
+    bool active;         // inside the domain
+    bool interior;       // in the tile interior and inside the domain
+    bool wW, wE, wS, wN; // next to a (non-periodic) wall on that side
+    int slot;            // LDS index of the cell in a plane
+    int oxs, oys;        // first stencil column / row relative to the cell
+    S d1x[3], d2x[3], d1y[3], d2y[3];   // 3-point derivative weights
+    S hxw, hxe, hys, hyn;                // face position minus cell centre
 };
 
-// Fill LDS planes q0 .. q0+nqs-1 with B = cc X + ce E over the halo tile.
-template <class S, bool DELTA>
-__device__ __forceinline__ void lq_fill(const SweepParams &p, const LQStage &a, LQShared<S> sh,
-                                        int i0, int j0, int q0, int nqs)
+template <class S>
+__device__ __forceinline__ RingCell<S> ring_cell(const SweepParams &p, int i0, int j0)
 {
-    const int TX = p.tile_x, TY = p.tile_y, HX = TX + 4;
-    const int plane = HX * (TY + 4);
-    const S *__restrict__ X = (const S *)a.X;
-    const long long n = p.ncell;
-    for (int c = threadIdx.x; c < plane; c += blockDim.x) {
-        const int hx = c % HX, hy = c / HX;
-        int gi = i0 + hx - 2, gj = j0 + hy - 2;
-        bool in = true;
-        if (p.perx) gi = wrapi(gi, p.nx); else in = in && gi >= 0 && gi < p.nx;
-        if (p.pery) gj = wrapi(gj, p.ny); else in = in && gj >= 0 && gj < p.ny;
-        S ec[6];
+    const int TX = p.tile_x, HX2 = TX + 2;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    RingCell<S> r;
+    int gi = i0 - 1 + lx, gj = j0 - 1 + ly;
+    bool in = true;
+    if (p.perx) gi = wrapi(gi, p.nx); else in = in && gi >= 0 && gi < p.nx;
+    if (p.pery) gj = wrapi(gj, p.ny); else in = in && gj >= 0 && gj < p.ny;
+    r.i = gi;
+    r.j = gj;
+    r.active = in;
+    r.interior = in && lx >= 1 && lx <= TX - 2 && ly >= 1 && ly <= p.tile_y - 2 && i0 - 1 + lx < p.nx &&
+                 j0 - 1 + ly < p.ny;
+    r.slot = (ly + 1) * HX2 + (lx + 1);
+    r.wW = in && !p.perx && gi == 0;
+    r.wE = in && !p.perx && gi == p.nx - 1;
+    r.wS = in && !p.pery && gj == 0;
+    r.wN = in && !p.pery && gj == p.ny - 1;
+    const int ci = in ? gi : 0, cj = in ? gj : 0;
+    // cells outside the domain: a central stencil with zero weights (reads stay
+    // inside the plane; the values are not used)
+    r.oxs = in ? p.g.sx_off[ci] : -1;
+    r.oys = in ? p.g.sy_off[cj] : -1;
 #pragma unroll
-        for (int k = 0; k < 6; k++) ec[k] = sh.ecoef[k * plane + c];
-        const S cc = sh.ecoef[6 * plane + c];
-        const long long cell = (long long)gj * p.nx + gi;
-        for (int s = 0; s < nqs; s++) {
-            const int q = q0 + s;
-            S v = (S)0;
-            if (in) {
-                const S e = eval_rt(ec, (S)p.xi[q], (S)p.eta[q]);
-                v = fmaS(cc, X[q * n + cell], DELTA ? e : (S)p.w[q] * e);
-            }
-            sh.planes[s * plane + c] = v;
-        }
+    for (int k = 0; k < 3; k++) {
+        r.d1x[k] = in ? (S)p.g.sx_d1[3 * ci + k] : (S)0;
+        r.d2x[k] = in ? (S)p.g.sx_d2[3 * ci + k] : (S)0;
+        r.d1y[k] = in ? (S)p.g.sy_d1[3 * cj + k] : (S)0;
+        r.d2y[k] = in ? (S)p.g.sy_d2[3 * cj + k] : (S)0;
     }
+    r.hxw = (S)p.g.dxr[ci];       // x_{i-1/2} - x_i
+    r.hxe = (S)p.g.dxl[ci + 1];   // x_{i+1/2} - x_i
+    r.hys = (S)p.g.dyr[cj];
+    r.hyn = (S)p.g.dyl[cj + 1];
+    return r;
 }
 
-// Once per block: equilibrium coefficients (scaled by ce) and cc of every halo cell.
+// Derivatives of B at the thread's cell from one LDS plane.
+template <class S>
+struct Deriv {
+    S b0, bx, by, bxx, byy, bxy;
+};
+
+template <class S>
+__device__ __forceinline__ Deriv<S> derivs(const RingCell<S> &r, const S *P, int HX2)
+{
+    Deriv<S> d;
+    d.b0 = P[r.slot];
+    S rows[3];
+    d.bx = d.bxx = d.by = d.byy = (S)0;
+#pragma unroll
+    for (int l = 0; l < 3; l++) {
+        const S *row = P + r.slot + (r.oys + l) * HX2 + r.oxs;
+        S acc = (S)0;
+#pragma unroll
+        for (int k = 0; k < 3; k++) acc = fmaS(r.d1x[k], row[k], acc);
+        rows[l] = acc;
+    }
+    const S *rw = P + r.slot + r.oxs;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        d.bx = fmaS(r.d1x[k], rw[k], d.bx);
+        d.bxx = fmaS(r.d2x[k], rw[k], d.bxx);
+    }
+#pragma unroll
+    for (int l = 0; l < 3; l++) {
+        const S v = P[r.slot + (r.oys + l) * HX2];
+        d.by = fmaS(r.d1y[l], v, d.by);
+        d.byy = fmaS(r.d2y[l], v, d.byy);
+    }
+    d.bxy = (S)0;
+#pragma unroll
+    for (int l = 0; l < 3; l++) d.bxy = fmaS(r.d1y[l], rows[l], d.bxy);
+    return d;
+}
+
+// B0 + dx Bx + dy By + kappa (dx^2 Bxx + 2 dx dy Bxy + dy^2 Byy)
+template <class S>
+__device__ __forceinline__ S expand(const Deriv<S> &d, S dx, S dy, S kappa)
+{
+    const S t = fmaS(dx, d.bxx, (S)2 * dy * d.bxy);
+    const S u = fmaS(kappa, t, d.bx);
+    S v = fmaS(dx, u, d.b0);
+    const S w = fmaS(kappa * dy, d.byy, d.by);
+    return fmaS(dy, w, v);
+}
+
+// Shared memory of an any-size block.
+template <class S>
+struct LQShared {
+    S *planes;   // [QS][plane] B over the tile and a 2-cell halo
+    S *ecoef;    // [7][plane] scaled equilibrium coefficients and transform weight
+    S *xch;      // [4][QS][TX*TY] interface contributions W, E, S, N (update)
+};
+
+template <class S>
+__device__ __forceinline__ LQShared<S> lq_shared(const SweepParams &p)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int plane = (p.tile_x + 2) * (p.tile_y + 2);
+    LQShared<S> sh;
+    sh.planes = reinterpret_cast<S *>(smem_raw);
+    sh.ecoef = sh.planes + p.lq_qs * plane;
+    sh.xch = sh.ecoef + 7 * plane;
+    return sh;
+}
+
+// Once per block: equilibrium coefficients (scaled by ce) and cc of every LDS cell.
 template <class S, bool DELTA>
 __device__ __forceinline__ void lq_prepare(const SweepParams &p, const LQStage &a, LQShared<S> sh,
                                            int i0, int j0)
 {
-    const int TX = p.tile_x, TY = p.tile_y, HX = TX + 4;
-    const int plane = HX * (TY + 4);
+    const int HX2 = p.tile_x + 2;
+    const int plane = HX2 * (p.tile_y + 2);
     for (int c = threadIdx.x; c < plane; c += blockDim.x) {
-        const int hx = c % HX, hy = c / HX;
+        const int hx = c % HX2, hy = c / HX2;
         int gi = i0 + hx - 2, gj = j0 + hy - 2;
         bool in = true;
         if (p.perx) gi = wrapi(gi, p.nx); else in = in && gi >= 0 && gi < p.nx;
@@ -132,137 +237,168 @@ __device__ __forceinline__ void lq_prepare(const SweepParams &p, const LQStage &
     }
 }
 
-// Interface value of x-face fi (cells fi-1 | fi) in row j for velocity (xq, yq);
-// hxr is the LDS column of cell fi.  Returns false for a velocity leaving a
-// diffuse wall (value set later from the wall density).
-template <class S>
-__device__ __forceinline__ bool lq_xface(const SweepParams &p, const S *P, int HX, int fi, int hxr,
-                                         int hyo, int j, double xq, double yq, double h, double &v)
+// Fill LDS planes q0 .. q0+nqs-1 with B = cc X + ce E (zero outside the domain).
+template <class S, bool DELTA>
+__device__ __forceinline__ void lq_fill(const SweepParams &p, const LQStage &a, LQShared<S> sh,
+                                        int i0, int j0, int q0, int nqs)
 {
-    const double dy = -yq * h;
-    if (!p.perx && fi == 0) {
-        if (xq > 0.0) return false;
-        v = expand_general(p, P, HX, hxr, hyo, 0, j, p.g.dxr[0] - xq * h, dy);
-    } else if (!p.perx && fi == p.nx) {
-        if (xq < 0.0) return false;
-        v = expand_general(p, P, HX, hxr - 1, hyo, p.nx - 1, j, p.g.dxl[p.nx] - xq * h, dy);
-    } else {
-        const int giL = wrapi(fi - 1, p.nx), giR = wrapi(fi, p.nx);
-        if (xq > 0.0) {
-            v = expand_general(p, P, HX, hxr - 1, hyo, giL, j, p.g.dxl[fi] - xq * h, dy);
-        } else if (xq < 0.0) {
-            v = expand_general(p, P, HX, hxr, hyo, giR, j, p.g.dxr[fi] - xq * h, dy);
-        } else {
-            v = 0.5 * (expand_general(p, P, HX, hxr - 1, hyo, giL, j, p.g.dxl[fi], dy) +
-                       expand_general(p, P, HX, hxr, hyo, giR, j, p.g.dxr[fi], dy));
+    constexpr int QS = lq_group<DELTA>();
+    const int HX2 = p.tile_x + 2;
+    const int plane = HX2 * (p.tile_y + 2);
+    const S *__restrict__ X = (const S *)a.X;
+    const cptr<S> MO = mono_table<S>(p);
+    const cptr<double> W = as_const(p.w);
+    const size_t n = (size_t)p.ncell;
+    for (int c = threadIdx.x; c < plane; c += blockDim.x) {
+        const int hx = c % HX2, hy = c / HX2;
+        int gi = i0 + hx - 2, gj = j0 + hy - 2;
+        bool in = true;
+        if (p.perx) gi = wrapi(gi, p.nx); else in = in && gi >= 0 && gi < p.nx;
+        if (p.pery) gj = wrapi(gj, p.ny); else in = in && gj >= 0 && gj < p.ny;
+        const size_t cell = in ? (size_t)gj * p.nx + gi : 0;
+        S xv[QS];
+#pragma unroll
+        for (int s = 0; s < QS; s++) xv[s] = (in && s < nqs) ? X[(size_t)(q0 + s) * n + cell] : (S)0;
+        S ec[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) ec[k] = sh.ecoef[k * plane + c];
+        const S cc = sh.ecoef[6 * plane + c];
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            if (s >= nqs) break;
+            const int q = q0 + s;
+            const cptr<S> m = MO + 9 * q;   // x, y, xx, xy, yy, ...
+            S e = ec[0];
+            e = fmaS(m[0], ec[1], e);
+            e = fmaS(m[1], ec[2], e);
+            e = fmaS(m[2], ec[3], e);
+            e = fmaS(m[3], ec[4], e);
+            e = fmaS(m[4], ec[5], e);
+            // ec and cc are zero outside the domain
+            sh.planes[s * plane + c] = fmaS(cc, xv[s], DELTA ? e : (S)W[q] * e);
         }
     }
-    return true;
 }
 
+// Interface values of one velocity at the faces the thread's cell is upwind
+// of (zero elsewhere): W, E, S, N.  A velocity parallel to a face gets half
+// of each side's expansion, or all of the interior cell's at a wall.  sg:
+// bit 0 xi > 0, bit 1 xi < 0, bit 2 eta > 0, bit 3 eta < 0 (uniform).
 template <class S>
-__device__ __forceinline__ bool lq_yface(const SweepParams &p, const S *P, int HX, int fj, int hyr,
-                                         int hxo, int i, double xq, double yq, double h, double &v)
+__device__ __forceinline__ void owned_faces(const RingCell<S> &r, const Deriv<S> &d, int sg, S xh, S yh,
+                                            S kappa, S (&f)[4])
 {
-    const double dx = -xq * h;
-    if (!p.pery && fj == 0) {
-        if (yq > 0.0) return false;
-        v = expand_general(p, P, HX, hxo, hyr, i, 0, dx, p.g.dyr[0] - yq * h);
-    } else if (!p.pery && fj == p.ny) {
-        if (yq < 0.0) return false;
-        v = expand_general(p, P, HX, hxo, hyr - 1, i, p.ny - 1, dx, p.g.dyl[p.ny] - yq * h);
-    } else {
-        const int gjS = wrapi(fj - 1, p.ny), gjN = wrapi(fj, p.ny);
-        if (yq > 0.0) {
-            v = expand_general(p, P, HX, hxo, hyr - 1, i, gjS, dx, p.g.dyl[fj] - yq * h);
-        } else if (yq < 0.0) {
-            v = expand_general(p, P, HX, hxo, hyr, i, gjN, dx, p.g.dyr[fj] - yq * h);
-        } else {
-            v = 0.5 * (expand_general(p, P, HX, hxo, hyr - 1, i, gjS, dx, p.g.dyl[fj]) +
-                       expand_general(p, P, HX, hxo, hyr, i, gjN, dx, p.g.dyr[fj]));
-        }
+    f[0] = f[1] = f[2] = f[3] = (S)0;
+    if (!r.active) return;
+    // x-faces: dy = -eta h
+    if (sg & 1) f[1] = expand(d, r.hxe - xh, -yh, kappa);
+    else if (sg & 2) f[0] = expand(d, r.hxw - xh, -yh, kappa);
+    else {
+        f[0] = (r.wW ? (S)1 : (S)0.5) * expand(d, r.hxw, -yh, kappa);
+        f[1] = (r.wE ? (S)1 : (S)0.5) * expand(d, r.hxe, -yh, kappa);
     }
-    return true;
+    if (sg & 4) f[3] = expand(d, -xh, r.hyn - yh, kappa);
+    else if (sg & 8) f[2] = expand(d, -xh, r.hys - yh, kappa);
+    else {
+        f[2] = (r.wS ? (S)1 : (S)0.5) * expand(d, -xh, r.hys, kappa);
+        f[3] = (r.wN ? (S)1 : (S)0.5) * expand(d, -xh, r.hyn, kappa);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// lq_faces
+// lq_faces: partial interface moments of a q-chunk.
 // ---------------------------------------------------------------------------
 template <class S, bool DELTA>
 __device__ void lq_faces_body(const SweepParams &p, const LQStage &a, int tile, int chunk)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int TX = p.tile_x, TY = p.tile_y, HX = TX + 4;
-    const int plane = HX * (TY + 4);
-    LQShared<S> sh;
-    sh.planes = reinterpret_cast<S *>(smem_raw);
-    sh.ecoef = sh.planes + p.lq_qs * plane;
-    const int gx = (p.nx + TX - 1) / TX;
-    const int i0 = (tile % gx) * TX, j0 = (tile / gx) * TY;
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int i = i0 + lx, j = j0 + ly;
-    const bool valid = i < p.nx && j < p.ny;
+    const int TX = p.tile_x, TY = p.tile_y, HX2 = TX + 2;
+    const int plane = HX2 * (TY + 2);
+    LQShared<S> sh = lq_shared<S>(p);
+    const int gx = (p.nx + TX - 3) / (TX - 2);
+    const int i0 = (tile % gx) * (TX - 2), j0 = (tile / gx) * (TY - 2);
     const int q0 = chunk * p.lq_chunk, q1 = min(p.nq, q0 + p.lq_chunk);
+    const RingCell<S> r = ring_cell<S>(p, i0, j0);
+    const S kappa = (S)p.kappa, hs = (S)a.h;
+    constexpr int QS = lq_group<DELTA>();
+    const cptr<S> MO = mono_table<S>(p);
+    const cptr<double> WM = as_const(p.lq_wm), XI = as_const(p.xi), ETA = as_const(p.eta);
+    const cptr<int> SG = as_const(p.lq_sgn);
+    // domain-boundary faces of the cell (diffuse-wall numerators)
+    const bool wallW = r.wW, wallE = r.wE, wallS = r.wS, wallN = r.wN;
 
     lq_prepare<S, DELTA>(p, a, sh, i0, j0);
-    // owned faces: W (x-face i), S (y-face j), and the E / N domain-boundary faces
-    const bool ownE = !p.perx && i == p.nx - 1;
-    const bool ownN = !p.pery && j == p.ny - 1;
-    double acc[4][4];   // faces W, S, E, N x (sum m x, sum m xi x, sum m eta x, diffuse numerator)
+    double acc[4][4];   // faces W, E, S, N x (sum m x, sum m xi x, sum m eta x, diffuse numerator)
 #pragma unroll
     for (int f = 0; f < 4; f++)
 #pragma unroll
         for (int k = 0; k < 4; k++) acc[f][k] = 0.0;
-    const double h = a.h;
-    for (int qa = q0; qa < q1; qa += p.lq_qs) {
-        const int nqs = min(p.lq_qs, q1 - qa);
+    for (int qa = q0; qa < q1; qa += QS) {
+        const int nqs = min(QS, q1 - qa);
         __syncthreads();
         lq_fill<S, DELTA>(p, a, sh, i0, j0, qa, nqs);
         __syncthreads();
-        if (!valid) continue;
-        for (int s = 0; s < nqs; s++) {
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            if (s >= nqs) break;
             const int q = qa + s;
-            const double xq = p.xi[q], yq = p.eta[q];
-            const double m = DELTA ? p.w[q] : 1.0;
-            const S *P = sh.planes + s * plane;
-            double v;
-            // west face of the cell
-            if (lq_xface(p, P, HX, i, lx + 2, ly + 2, j, xq, yq, h, v)) {
-                acc[0][0] = __builtin_fma(m, v, acc[0][0]);
-                acc[0][1] = __builtin_fma(m * xq, v, acc[0][1]);
-                acc[0][2] = __builtin_fma(m * yq, v, acc[0][2]);
-                if (!p.perx && i == 0 && xq < 0.0) acc[0][3] = __builtin_fma(-xq * m, v, acc[0][3]);
-            }
-            if (lq_yface(p, P, HX, j, ly + 2, lx + 2, i, xq, yq, h, v)) {
-                acc[1][0] = __builtin_fma(m, v, acc[1][0]);
-                acc[1][1] = __builtin_fma(m * xq, v, acc[1][1]);
-                acc[1][2] = __builtin_fma(m * yq, v, acc[1][2]);
-                if (!p.pery && j == 0 && yq < 0.0) acc[1][3] = __builtin_fma(-yq * m, v, acc[1][3]);
-            }
-            if (ownE && lq_xface(p, P, HX, i + 1, lx + 3, ly + 2, j, xq, yq, h, v)) {
-                acc[2][0] = __builtin_fma(m, v, acc[2][0]);
-                acc[2][1] = __builtin_fma(m * xq, v, acc[2][1]);
-                acc[2][2] = __builtin_fma(m * yq, v, acc[2][2]);
-                if (xq > 0.0) acc[2][3] = __builtin_fma(xq * m, v, acc[2][3]);
-            }
-            if (ownN && lq_yface(p, P, HX, j + 1, ly + 3, lx + 2, i, xq, yq, h, v)) {
-                acc[3][0] = __builtin_fma(m, v, acc[3][0]);
-                acc[3][1] = __builtin_fma(m * xq, v, acc[3][1]);
-                acc[3][2] = __builtin_fma(m * yq, v, acc[3][2]);
-                if (yq > 0.0) acc[3][3] = __builtin_fma(yq * m, v, acc[3][3]);
-            }
+            const cptr<S> mo = MO + 9 * q;
+            const int sg = SG[q];
+            const Deriv<S> d = derivs<S>(r, sh.planes + s * plane, HX2);
+            S fv[4];
+            owned_faces<S>(r, d, sg, mo[0] * hs, mo[1] * hs, kappa, fv);
+            const cptr<double> m = WM + 3 * q;
+            const double m0 = m[0], mx = m[1], my = m[2];
+            // moments of the faces this cell computed for this velocity
+            auto add = [&](int f) {
+                const double v = (double)fv[f];
+                acc[f][0] = __builtin_fma(m0, v, acc[f][0]);
+                acc[f][1] = __builtin_fma(mx, v, acc[f][1]);
+                acc[f][2] = __builtin_fma(my, v, acc[f][2]);
+            };
+            if (sg & 1) add(1);
+            else if (sg & 2) add(0);
+            else { add(0); add(1); }
+            if (sg & 4) add(3);
+            else if (sg & 8) add(2);
+            else { add(2); add(3); }
+            // arriving at a wall: sum of |xi.n| m fbar (eq. of the diffuse-scattering rule)
+            const double xq = XI[q], yq = ETA[q];
+            if (wallW && (sg & 2)) acc[0][3] = __builtin_fma(-xq * m0, (double)fv[0], acc[0][3]);
+            if (wallE && (sg & 1)) acc[1][3] = __builtin_fma(xq * m0, (double)fv[1], acc[1][3]);
+            if (wallS && (sg & 8)) acc[2][3] = __builtin_fma(-yq * m0, (double)fv[2], acc[2][3]);
+            if (wallN && (sg & 4)) acc[3][3] = __builtin_fma(yq * m0, (double)fv[3], acc[3][3]);
         }
     }
-    if (!valid) return;
-    const long long nface = (long long)(p.nx + 1) * p.ny + (long long)p.nx * (p.ny + 1);
-    double *part = a.face_part + (long long)chunk * nface * 4;
-    long long fid[4] = {xface_id(p, i, j), yface_id(p, i, j), xface_id(p, i + 1, j), yface_id(p, i, j + 1)};
-    const bool own[4] = {true, true, ownE, ownN};
+    // combine the two sides of every face: the tile writes the west and south
+    // faces of its interior cells (and the east / north domain faces)
+    __syncthreads();
+    double *xa = reinterpret_cast<double *>(sh.planes);   // [16][TX*TY], fits the plane area
+    const int NT = TX * TY, t = threadIdx.x;
 #pragma unroll
     for (int f = 0; f < 4; f++)
-        if (own[f])
 #pragma unroll
-            for (int k = 0; k < 4; k++) part[4 * fid[f] + k] = acc[f][k];
+        for (int k = 0; k < 4; k++) xa[(f * 4 + k) * NT + t] = acc[f][k];
+    __syncthreads();
+    if (!r.interior) return;
+    const long long nface = (long long)(p.nx + 1) * p.ny + (long long)p.nx * (p.ny + 1);
+    double *part = a.face_part + (long long)chunk * nface * 4;
+    const int tl = t - 1, tb = t - TX;   // west and south neighbours
+    const long long fw = xface_id(p, r.i, r.j), fs = yface_id(p, r.i, r.j);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        part[4 * fw + k] = acc[0][k] + xa[(1 * 4 + k) * NT + tl];
+        part[4 * fs + k] = acc[2][k] + xa[(3 * 4 + k) * NT + tb];
+    }
+    if (wallE) {
+        const long long fe = xface_id(p, r.i + 1, r.j);
+#pragma unroll
+        for (int k = 0; k < 4; k++) part[4 * fe + k] = acc[1][k];
+    }
+    if (wallN) {
+        const long long fn = yface_id(p, r.i, r.j + 1);
+#pragma unroll
+        for (int k = 0; k < 4; k++) part[4 * fn + k] = acc[3][k];
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -319,43 +455,45 @@ __device__ void lq_face_reduce_body(const SweepParams &p, const LQStage &a, bool
 }
 
 // ---------------------------------------------------------------------------
-// lq_update
+// lq_update: recovery, micro-flux and stage output of a q-chunk.  The part of
+// the micro-flux linear in the interface values is formed from the values the
+// upwind cells computed (exchanged through LDS); the equilibrium part of the
+// recovered interface values (eq. recover2f) and every equilibrium term of the
+// output are one cubic polynomial in xi per cell, built once.
 // ---------------------------------------------------------------------------
 template <class S, bool DELTA>
 __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int tile, int chunk)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int TX = p.tile_x, TY = p.tile_y, HX = TX + 4;
-    const int plane = HX * (TY + 4);
-    LQShared<S> sh;
-    sh.planes = reinterpret_cast<S *>(smem_raw);
-    sh.ecoef = sh.planes + p.lq_qs * plane;
-    const int gx = (p.nx + TX - 1) / TX;
-    const int i0 = (tile % gx) * TX, j0 = (tile / gx) * TY;
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const int i = i0 + lx, j = j0 + ly;
-    const bool valid = i < p.nx && j < p.ny;
+    const int TX = p.tile_x, TY = p.tile_y, HX2 = TX + 2;
+    const int plane = HX2 * (TY + 2);
+    constexpr int QS = lq_group<DELTA>();
+    const int NT = TX * TY, t = threadIdx.x;
+    LQShared<S> sh = lq_shared<S>(p);
+    const int gx = (p.nx + TX - 3) / (TX - 2);
+    const int i0 = (tile % gx) * (TX - 2), j0 = (tile / gx) * (TY - 2);
     const int q0 = chunk * p.lq_chunk, q1 = min(p.nq, q0 + p.lq_chunk);
     const long long n = p.ncell;
-    const long long cell = (long long)j * p.nx + i;
+    const RingCell<S> r = ring_cell<S>(p, i0, j0);
+    const S kappa = (S)p.kappa;
     const double dt = p.dt, h = a.h;
+    const size_t cell = (size_t)r.j * p.nx + r.i;
 
     lq_prepare<S, DELTA>(p, a, sh, i0, j0);
 
-    // per-thread face data: equilibrium coefficients (scaled by beta), alpha,
-    // diffuse-wall densities; own-cell output coefficients
-    S eb[4][6];
-    S alpha_s[4];
-    double rw[4] = {0, 0, 0, 0};
+    // per-cell data of interior threads
+    S alpha[4] = {0, 0, 0, 0};
+    S rws[4] = {0, 0, 0, 0};
     bool dsf[4] = {false, false, false, false};
-    S ownE[6], ownE2[6];   // stage A: 5/4 e1 E^n ; stage C: a_En E^n, a_Ep E'
-    S kx_own = 0, kf_own = 0, aL = 0;
-    S cx = 0, cy = 0;
-    if (valid) {
+    S M[10];   // 1, x, y, xx, xy, yy, xxx, xxy, xyy, yyy
+    S kx_own = 0, kf_own = 0, aL = 0, cx = 0, cy = 0;
+#pragma unroll
+    for (int k = 0; k < 10; k++) M[k] = (S)0;
+    if (r.interior) {
+        const int i = r.i, j = r.j;
         const long long fid[4] = {xface_id(p, i, j), xface_id(p, i + 1, j), yface_id(p, i, j),
                                   yface_id(p, i, j + 1)};
         const double tau_o = p.tau_field ? p.tau[cell] : p.tau0;
-        double tb[4];
+        double tb[4] = {tau_o, tau_o, tau_o, tau_o};
         if (p.tau_field) {
             const int im = p.perx ? wrapi(i - 1, p.nx) : (i > 0 ? i - 1 : i);
             const int ip = p.perx ? wrapi(i + 1, p.nx) : (i < p.nx - 1 ? i + 1 : i);
@@ -366,40 +504,43 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int tile,
             tb[2] = 0.5 * (tau_o + p.tau[(long long)jm * p.nx + i]);
             tb[3] = 0.5 * (tau_o + p.tau[(long long)jp * p.nx + i]);
         }
+        double be[4];
+        EPoly ef[4];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             const double *fm = a.face_mom + 8 * fid[k];
-            double al, be;
+            double al;
             if (p.tau_field) {
                 al = 2.0 * tb[k] / (2.0 * tb[k] + h);
-                be = h / (2.0 * tb[k] + h);
+                be[k] = h / (2.0 * tb[k] + h);
             } else {
                 al = p.uc.alpha[a.stage];
-                be = p.uc.beta[a.stage];
+                be[k] = p.uc.beta[a.stage];
             }
-            const EPoly e = epoly(fm[0], fm[1], fm[2], fm[3], p.iRT, 1.0, DELTA);
-            eb[k][0] = (S)(be * e.c0); eb[k][1] = (S)(be * e.c1x); eb[k][2] = (S)(be * e.c1y);
-            eb[k][3] = (S)(be * e.c2xx); eb[k][4] = (S)(be * e.c2xy); eb[k][5] = (S)(be * e.c2yy);
-            alpha_s[k] = (S)al;
-            rw[k] = fm[4];
+            ef[k] = epoly(fm[0], fm[1], fm[2], fm[3], p.iRT, 1.0, DELTA);
+            alpha[k] = (S)al;
+            rws[k] = (S)fm[4];
         }
         dsf[0] = !p.perx && i == 0 && p.bc[0] == 2;
         dsf[1] = !p.perx && i == p.nx - 1 && p.bc[1] == 2;
         dsf[2] = !p.pery && j == 0 && p.bc[2] == 2;
         dsf[3] = !p.pery && j == p.ny - 1 && p.bc[3] == 2;
-        cx = (S)(-(p.uniform ? p.inv_dx : p.g.inv_dx[i]));
-        cy = (S)(-(p.uniform ? p.inv_dy : p.g.inv_dy[j]));
+        const double idx = p.uniform ? p.inv_dx : p.g.inv_dx[i];
+        const double idy = p.uniform ? p.inv_dy : p.g.inv_dy[j];
+        cx = (S)(-idx);
+        cy = (S)(-idy);
         const double c1 = p.tau_field ? (12.0 * tau_o - dt) / (12.0 * tau_o + 3.0 * dt) : p.uc.c1;
         const double e1 = p.tau_field ? 4.0 * dt / (12.0 * tau_o + 3.0 * dt) : p.uc.e1;
         const double *mx = a.momX + 4 * cell;
         const EPoly ex = epoly(mx[0], mx[1], mx[2], mx[3], p.iRT, 1.0, DELTA);
+        double EO[6], aLd;
         if (a.stage == 0) {
             // tilde f^+(t_n) = (5/4 c1 - 1/4) fhat + 5/4 e1 E^n (eq. f_tilde_1_3)
             const double k = 1.25 * e1;
-            ownE[0] = (S)(k * ex.c0); ownE[1] = (S)(k * ex.c1x); ownE[2] = (S)(k * ex.c1y);
-            ownE[3] = (S)(k * ex.c2xx); ownE[4] = (S)(k * ex.c2xy); ownE[5] = (S)(k * ex.c2yy);
+            EO[0] = k * ex.c0; EO[1] = k * ex.c1x; EO[2] = k * ex.c1y;
+            EO[3] = k * ex.c2xx; EO[4] = k * ex.c2xy; EO[5] = k * ex.c2yy;
             kx_own = (S)(1.25 * c1 - 0.25);
-            aL = (S)(dt / 3.0);
+            aLd = dt / 3.0;
         } else {
             double a_f = p.uc.a_f, a_En = p.uc.a_En, a_G = p.uc.a_G, a_Ep = p.uc.a_Ep;
             if (p.tau_field) {
@@ -411,66 +552,116 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int tile,
             }
             const double *mf = a.momF + 4 * cell;
             const EPoly en = epoly(mf[0], mf[1], mf[2], mf[3], p.iRT, 1.0, DELTA);
-            ownE[0] = (S)(a_En * en.c0); ownE[1] = (S)(a_En * en.c1x); ownE[2] = (S)(a_En * en.c1y);
-            ownE[3] = (S)(a_En * en.c2xx); ownE[4] = (S)(a_En * en.c2xy); ownE[5] = (S)(a_En * en.c2yy);
-            ownE2[0] = (S)(a_Ep * ex.c0); ownE2[1] = (S)(a_Ep * ex.c1x); ownE2[2] = (S)(a_Ep * ex.c1y);
-            ownE2[3] = (S)(a_Ep * ex.c2xx); ownE2[4] = (S)(a_Ep * ex.c2xy); ownE2[5] = (S)(a_Ep * ex.c2yy);
+            EO[0] = a_En * en.c0 + a_Ep * ex.c0; EO[1] = a_En * en.c1x + a_Ep * ex.c1x;
+            EO[2] = a_En * en.c1y + a_Ep * ex.c1y; EO[3] = a_En * en.c2xx + a_Ep * ex.c2xx;
+            EO[4] = a_En * en.c2xy + a_Ep * ex.c2xy; EO[5] = a_En * en.c2yy + a_Ep * ex.c2yy;
             kx_own = (S)a_G;
             kf_own = (S)a_f;
-            aL = (S)(4.0 * dt / 7.0);
+            aLd = 4.0 * dt / 7.0;
         }
+        aL = (S)aLd;
+        // equilibrium part of L: -(xi/dx)(beta_e E_e - beta_w E_w) - (eta/dy)(beta_n E_n - beta_s E_s)
+        const double kx = -idx * aLd, ky = -idy * aLd;
+        double pe[4][6];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            pe[k][0] = ef[k].c0; pe[k][1] = ef[k].c1x; pe[k][2] = ef[k].c1y;
+            pe[k][3] = ef[k].c2xx; pe[k][4] = ef[k].c2xy; pe[k][5] = ef[k].c2yy;
+        }
+        double A[6], B[6];
+#pragma unroll
+        for (int c = 0; c < 6; c++) {
+            A[c] = be[1] * pe[1][c] - be[0] * pe[0][c];
+            B[c] = be[3] * pe[3][c] - be[2] * pe[2][c];
+        }
+        M[0] = (S)EO[0];
+        M[1] = (S)(EO[1] + kx * A[0]);
+        M[2] = (S)(EO[2] + ky * B[0]);
+        M[3] = (S)(EO[3] + kx * A[1]);
+        M[4] = (S)(EO[4] + kx * A[2] + ky * B[1]);
+        M[5] = (S)(EO[5] + ky * B[2]);
+        M[6] = (S)(kx * A[3]);
+        M[7] = (S)(kx * A[4] + ky * B[3]);
+        M[8] = (S)(kx * A[5] + ky * B[4]);
+        M[9] = (S)(ky * B[5]);
     }
     const S r0s = (S)(DELTA ? p.rho0 : 0.0);
     const S *__restrict__ X = (const S *)a.X;
     const S *__restrict__ F = (const S *)a.F;
     S *__restrict__ out = (S *)a.out;
+    const cptr<S> MO = mono_table<S>(p);
+    const cptr<double> WM = as_const(p.lq_wm), W = as_const(p.w), WE = as_const(p.wall_E);
+    const cptr<int> SG = as_const(p.lq_sgn);
+    const S hs = (S)h;
+    const size_t nn = (size_t)n;
     double m0 = 0, m1 = 0, m2 = 0;   // partial cell moments of the output
+    S *xw = sh.xch, *xe = sh.xch + QS * NT, *ys = sh.xch + 2 * QS * NT, *yn = sh.xch + 3 * QS * NT;
 
-    for (int qa = q0; qa < q1; qa += p.lq_qs) {
-        const int nqs = min(p.lq_qs, q1 - qa);
+    for (int qa = q0; qa < q1; qa += QS) {
+        const int nqs = min(QS, q1 - qa);
         __syncthreads();
         lq_fill<S, DELTA>(p, a, sh, i0, j0, qa, nqs);
         __syncthreads();
-        if (!valid) continue;
-        for (int s = 0; s < nqs; s++) {
-            const int q = qa + s;
-            const double xq = p.xi[q], yq = p.eta[q];
-            const S xs = (S)xq, ys = (S)yq;
-            const S sq = DELTA ? (S)1 : (S)p.w[q];
-            const S *P = sh.planes + s * plane;
-            double vv[4];
-            bool ok[4];
-            ok[0] = lq_xface(p, P, HX, i, lx + 2, ly + 2, j, xq, yq, h, vv[0]);
-            ok[1] = lq_xface(p, P, HX, i + 1, lx + 3, ly + 2, j, xq, yq, h, vv[1]);
-            ok[2] = lq_yface(p, P, HX, j, ly + 2, lx + 2, i, xq, yq, h, vv[2]);
-            ok[3] = lq_yface(p, P, HX, j + 1, ly + 3, lx + 2, i, xq, yq, h, vv[3]);
-            S fb[4];
+        // interface values of the faces this cell is upwind of
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-                S bar;
-                if (ok[k]) bar = (S)vv[k];
-                else bar = dsf[k] ? (S)rw[k] * (S)p.wall_E[k * p.nq + q] - r0s : (S)0;
-                fb[k] = fmaS(alpha_s[k], bar, sq * eval_rt(eb[k], xs, ys));
-            }
-            const S L = fmaS(xs * cx, fb[1] - fb[0], ys * cy * (fb[3] - fb[2]));
-            S R;
-            const S xo = X[q * n + cell];
-            if (a.stage == 0) {
-                R = fmaS(kx_own, xo, sq * eval_rt(ownE, xs, ys));
-            } else {
-                const S fo = F[q * n + cell];
-                R = fmaS(kf_own, fo, fmaS(kx_own, xo, sq * (eval_rt(ownE, xs, ys) + eval_rt(ownE2, xs, ys))));
-            }
-            const S y = fmaS(aL, L, R);
-            out[q * n + cell] = y;
-            const double m = DELTA ? p.w[q] : 1.0;
+        for (int s = 0; s < QS; s++) {
+            if (s >= nqs) break;
+            const int q = qa + s;
+            const cptr<S> mo = MO + 9 * q;
+            const Deriv<S> d = derivs<S>(r, sh.planes + s * plane, HX2);
+            S fv[4];
+            owned_faces<S>(r, d, SG[q], mo[0] * hs, mo[1] * hs, kappa, fv);
+            xw[s * NT + t] = fv[0];
+            xe[s * NT + t] = fv[1];
+            ys[s * NT + t] = fv[2];
+            yn[s * NT + t] = fv[3];
+        }
+        __syncthreads();
+        if (!r.interior) continue;
+        S xo[QS], fo[QS];
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            xo[s] = s < nqs ? X[(size_t)(qa + s) * nn + cell] : (S)0;
+            fo[s] = (a.stage != 0 && s < nqs) ? F[(size_t)(qa + s) * nn + cell] : (S)0;
+        }
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            if (s >= nqs) break;
+            const int q = qa + s;
+            const int sg = SG[q];
+            const cptr<S> mo = MO + 9 * q;
+            const int b = s * NT + t;
+            // face value = contributions of the cells on both sides
+            S fw, fe, fs, fn;
+            if (sg & 1) { fw = xe[b - 1]; fe = xe[b]; }
+            else if (sg & 2) { fw = xw[b]; fe = xw[b + 1]; }
+            else { fw = xe[b - 1] + xw[b]; fe = xe[b] + xw[b + 1]; }
+            if (sg & 4) { fs = yn[b - TX]; fn = yn[b]; }
+            else if (sg & 8) { fs = ys[b]; fn = ys[b + TX]; }
+            else { fs = yn[b - TX] + ys[b]; fn = yn[b] + ys[b + TX]; }
+            // velocities leaving a diffuse wall: fbar = E(rho_w, u_w)
+            if (dsf[0] && (sg & 1)) fw = rws[0] * (S)WE[q] - r0s;
+            if (dsf[1] && (sg & 2)) fe = rws[1] * (S)WE[p.nq + q] - r0s;
+            if (dsf[2] && (sg & 4)) fs = rws[2] * (S)WE[2 * p.nq + q] - r0s;
+            if (dsf[3] && (sg & 8)) fn = rws[3] * (S)WE[3 * p.nq + q] - r0s;
+            const S La = fmaS(mo[0] * cx, fmaS(alpha[1], fe, -alpha[0] * fw),
+                              mo[1] * cy * fmaS(alpha[3], fn, -alpha[2] * fs));
+            S Mq = M[0];
+#pragma unroll
+            for (int k = 0; k < 9; k++) Mq = fmaS(mo[k], M[k + 1], Mq);
+            const S sq = DELTA ? (S)1 : (S)W[q];
+            S R = kx_own * xo[s];
+            if (a.stage != 0) R = fmaS(kf_own, fo[s], R);
+            const S y = fmaS(aL, La, fmaS(sq, Mq, R));
+            out[(size_t)q * nn + cell] = y;
+            const cptr<double> w3 = WM + 3 * q;
             const double yd = (double)y;
-            m0 = __builtin_fma(m, yd, m0);
-            m1 = __builtin_fma(m * xq, yd, m1);
-            m2 = __builtin_fma(m * yq, yd, m2);
+            m0 = __builtin_fma(w3[0], yd, m0);
+            m1 = __builtin_fma(w3[1], yd, m1);
+            m2 = __builtin_fma(w3[2], yd, m2);
         }
     }
-    if (!valid) return;
+    if (!r.interior) return;
     double *cp = a.cell_part + ((long long)chunk * n + cell) * 4;
     cp[0] = m0; cp[1] = m1; cp[2] = m2; cp[3] = 0.0;
 }
@@ -535,14 +726,14 @@ __global__ void k_state_moments(const SweepParams p, const S *__restrict__ x, do
 template <class S, bool DELTA>
 __global__ void __launch_bounds__(256) lq_faces(const SweepParams p, const LQStage a)
 {
-    const int ntile = ((p.nx + p.tile_x - 1) / p.tile_x) * ((p.ny + p.tile_y - 1) / p.tile_y);
+    const int ntile = lq_ntile(p);
     lq_faces_body<S, DELTA>(p, a, blockIdx.x % ntile, blockIdx.x / ntile);
 }
 
 template <class S, bool DELTA>
 __global__ void __launch_bounds__(256) lq_update(const SweepParams p, const LQStage a)
 {
-    const int ntile = ((p.nx + p.tile_x - 1) / p.tile_x) * ((p.ny + p.tile_y - 1) / p.tile_y);
+    const int ntile = lq_ntile(p);
     lq_update_body<S, DELTA>(p, a, blockIdx.x % ntile, blockIdx.x / ntile);
 }
 
@@ -619,14 +810,19 @@ hipError_t launch_lq_stage_batched(bool delta, const SweepParams *P, const LQSta
 
 size_t lq_smem_bytes(const SweepParams &p, bool delta)
 {
-    const size_t plane = (size_t)(p.tile_x + 4) * (p.tile_y + 4);
-    return (delta ? 4 : 8) * plane * (p.lq_qs + 7);
+    // planes and equilibrium coefficients over the tile and halo, interface
+    // exchange; the interface-moment exchange of lq_faces (16 doubles per
+    // thread) reuses the same space
+    const size_t plane = (size_t)(p.tile_x + 2) * (p.tile_y + 2);
+    const size_t nt = (size_t)p.tile_x * p.tile_y;
+    const size_t a = (delta ? 4 : 8) * (plane * (p.lq_qs + 7) + 4 * (size_t)p.lq_qs * nt);
+    return std::max(a, 16 * 8 * nt);
 }
 
 template <class S, bool DELTA>
 static hipError_t lq_stage_t(const SweepParams &p, const LQStage &a, hipStream_t s, int part)
 {
-    const int ntile = ((p.nx + p.tile_x - 1) / p.tile_x) * ((p.ny + p.tile_y - 1) / p.tile_y);
+    const int ntile = lq_ntile(p);
     const dim3 blk(p.tile_x * p.tile_y);
     const size_t smem = lq_smem_bytes(p, DELTA);
     const long long nface = (long long)(p.nx + 1) * p.ny + (long long)p.nx * (p.ny + 1);
