@@ -488,16 +488,17 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     if (h->lat == 0) {
         // ring tiles (one block covers (lx - 2) x (ly - 2) cells); chunks: enough
         // workgroups to fill the chip, at least 16 velocities each
-        if (lx < 4 || ly < 4) {
+        if (lx < 4 || ly < 4 || (lx + 2) * (ly + 2) > 2 * lx * ly) {
             delete h;
             return fail(DUGKS_EINVAL, "any-size velocity sets need tiles of at least 4 x 4 threads");
         }
         const long long ntile = lq_ntile(p);
         int nch = (int)std::max(1LL, (2048 + ntile - 1) / ntile);
         nch = std::min(nch, std::max(1, nq / 16));
-        p.lq_chunk = (nq + nch - 1) / nch;
-        p.lq_nchunk = (nq + p.lq_chunk - 1) / p.lq_chunk;
         p.lq_qs = 4;
+        p.lq_chunk = (nq + nch - 1) / nch;
+        p.lq_chunk = (p.lq_chunk + p.lq_qs - 1) / p.lq_qs * p.lq_qs;   // whole plane groups
+        p.lq_nchunk = (nq + p.lq_chunk - 1) / p.lq_chunk;
     }
     // lattice kernels: one plane of the tile and its halo per velocity, plus one
     // spare element per plane (compile-time-shape kernels)
@@ -590,7 +591,16 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
         std::vector<int> sg(nq);
         for (int q = 0; q < nq; q++)
             sg[q] = (xi[q] > 0 ? 1 : 0) | (xi[q] < 0 ? 2 : 0) | (eta[q] > 0 ? 4 : 0) | (eta[q] < 0 ? 8 : 0);
-        UP(lw, p.lq_wm) UP(md, p.lq_mono_d) UP(mf, p.lq_mono_f) UP(sg, p.lq_sgn)
+        std::vector<int> gnz(nq / p.lq_qs + 1, 0);
+        for (int g = 0; g * p.lq_qs + p.lq_qs <= nq; g++) {
+            int ok = 1;
+            for (int k = 0; k < p.lq_qs; k++) {
+                const int q = g * p.lq_qs + k;
+                ok &= (xi[q] != 0.0) && (eta[q] != 0.0);
+            }
+            gnz[g] = ok;
+        }
+        UP(lw, p.lq_wm) UP(md, p.lq_mono_d) UP(mf, p.lq_mono_f) UP(sg, p.lq_sgn) UP(gnz, p.lq_gnz)
     }
     if (d->tau) {
         std::vector<double> vt(d->tau, d->tau + ncell);

@@ -74,6 +74,7 @@ struct SweepParams {
     const float *lq_mono_f;  // [nq][9] xi, eta, xi^2, xi eta, eta^2, xi^3, xi^2 eta, xi eta^2, eta^3
     const double *lq_mono_d;
     const int *lq_sgn;       // [nq] bit 0: xi > 0, 1: xi < 0, 2: eta > 0, 3: eta < 0
+    const int *lq_gnz;       // [nq / lq_qs + 1] group of lq_qs velocities complete, no zero component
 };
 
 // Per-stage arguments of the large-velocity-set kernels.

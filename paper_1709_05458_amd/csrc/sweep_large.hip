@@ -17,6 +17,7 @@
 #include "sweep_common.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace dk {
 
@@ -192,7 +193,6 @@ __device__ __forceinline__ S expand(const Deriv<S> &d, S dx, S dy, S kappa)
 template <class S>
 struct LQShared {
     S *planes;   // [QS][plane] B over the tile and a 2-cell halo
-    S *ecoef;    // [7][plane] scaled equilibrium coefficients and transform weight
     S *xch;      // [4][QS][TX*TY] interface contributions W, E, S, N (update)
 };
 
@@ -203,25 +203,40 @@ __device__ __forceinline__ LQShared<S> lq_shared(const SweepParams &p)
     const int plane = (p.tile_x + 2) * (p.tile_y + 2);
     LQShared<S> sh;
     sh.planes = reinterpret_cast<S *>(smem_raw);
-    sh.ecoef = sh.planes + p.lq_qs * plane;
-    sh.xch = sh.ecoef + 7 * plane;
+    sh.xch = sh.planes + p.lq_qs * plane;
     return sh;
 }
 
-// Once per block: equilibrium coefficients (scaled by ce) and cc of every LDS cell.
+// LDS cells a thread fills: at most two per thread (a (T+2)^2 plane over T^2
+// threads), with their global index and transform coefficients, set up once
+// per block.
+template <class S>
+struct FillSlots {
+    static constexpr int N = 2;
+    size_t cell[N];
+    bool use[N];      // slot exists (index < plane)
+    S ec[N][6], cc[N];
+};
+
+// Once per block: equilibrium coefficients (scaled by ce) and cc of every LDS
+// cell the thread fills (zero outside the domain).
 template <class S, bool DELTA>
-__device__ __forceinline__ void lq_prepare(const SweepParams &p, const LQStage &a, LQShared<S> sh,
-                                           int i0, int j0)
+__device__ __forceinline__ FillSlots<S> lq_prepare(const SweepParams &p, const LQStage &a, int i0, int j0)
 {
     const int HX2 = p.tile_x + 2;
     const int plane = HX2 * (p.tile_y + 2);
-    for (int c = threadIdx.x; c < plane; c += blockDim.x) {
+    FillSlots<S> f;
+#pragma unroll
+    for (int k = 0; k < FillSlots<S>::N; k++) {
+        const int c = threadIdx.x + k * blockDim.x;
+        f.use[k] = c < plane;
         const int hx = c % HX2, hy = c / HX2;
         int gi = i0 + hx - 2, gj = j0 + hy - 2;
-        bool in = true;
+        bool in = f.use[k];
         if (p.perx) gi = wrapi(gi, p.nx); else in = in && gi >= 0 && gi < p.nx;
         if (p.pery) gj = wrapi(gj, p.ny); else in = in && gj >= 0 && gj < p.ny;
         double ec[6] = {0, 0, 0, 0, 0, 0}, cc = 0.0;
+        f.cell[k] = in ? (size_t)gj * p.nx + gi : 0;
         if (in) {
             const long long cell = (long long)gj * p.nx + gi;
             const double *m = a.momX + 4 * cell;
@@ -232,52 +247,67 @@ __device__ __forceinline__ void lq_prepare(const SweepParams &p, const LQStage &
             ec[3] = ce * e.c2xx; ec[4] = ce * e.c2xy; ec[5] = ce * e.c2yy;
         }
 #pragma unroll
-        for (int k = 0; k < 6; k++) sh.ecoef[k * plane + c] = (S)ec[k];
-        sh.ecoef[6 * plane + c] = (S)cc;
+        for (int m = 0; m < 6; m++) f.ec[k][m] = (S)ec[m];
+        f.cc[k] = (S)cc;
     }
+    return f;
 }
 
-// Fill LDS planes q0 .. q0+nqs-1 with B = cc X + ce E (zero outside the domain).
+// Loads of a plane group for the thread's fill slots (issued one group ahead
+// of their use, so that their latency overlaps the previous group's work).
 template <class S, bool DELTA>
-__device__ __forceinline__ void lq_fill(const SweepParams &p, const LQStage &a, LQShared<S> sh,
-                                        int i0, int j0, int q0, int nqs)
+struct FillLoads {
+    S x[FillSlots<S>::N][lq_group<DELTA>()];
+};
+
+template <class S, bool DELTA>
+__device__ __forceinline__ void lq_load(const SweepParams &p, const LQStage &a, const FillSlots<S> &f, int q0,
+                                        int nqs, FillLoads<S, DELTA> &v)
 {
     constexpr int QS = lq_group<DELTA>();
-    const int HX2 = p.tile_x + 2;
-    const int plane = HX2 * (p.tile_y + 2);
     const S *__restrict__ X = (const S *)a.X;
+    const size_t n = (size_t)p.ncell;
+    // velocities past the end repeat the last one (valid addresses, values unused)
+#pragma unroll
+    for (int k = 0; k < FillSlots<S>::N; k++)
+#pragma unroll
+        for (int s = 0; s < QS; s++) v.x[k][s] = X[(size_t)min(q0 + s, p.nq - 1) * n + f.cell[k]];
+    (void)nqs;
+}
+
+// LDS planes q0 .. q0+nqs-1 of B = cc X + ce E (zero outside the domain).
+template <class S, bool DELTA>
+__device__ __forceinline__ void lq_store(const SweepParams &p, LQShared<S> sh, const FillSlots<S> &f, int q0,
+                                         int nqs, const FillLoads<S, DELTA> &v)
+{
+    constexpr int QS = lq_group<DELTA>();
+    const int plane = (p.tile_x + 2) * (p.tile_y + 2);
     const cptr<S> MO = mono_table<S>(p);
     const cptr<double> W = as_const(p.w);
-    const size_t n = (size_t)p.ncell;
-    for (int c = threadIdx.x; c < plane; c += blockDim.x) {
-        const int hx = c % HX2, hy = c / HX2;
-        int gi = i0 + hx - 2, gj = j0 + hy - 2;
-        bool in = true;
-        if (p.perx) gi = wrapi(gi, p.nx); else in = in && gi >= 0 && gi < p.nx;
-        if (p.pery) gj = wrapi(gj, p.ny); else in = in && gj >= 0 && gj < p.ny;
-        const size_t cell = in ? (size_t)gj * p.nx + gi : 0;
-        S xv[QS];
+    S mx[QS], my[QS], mxx[QS], mxy[QS], myy[QS], wq[QS];
 #pragma unroll
-        for (int s = 0; s < QS; s++) xv[s] = (in && s < nqs) ? X[(size_t)(q0 + s) * n + cell] : (S)0;
-        S ec[6];
+    for (int s = 0; s < QS; s++) {
+        const int q = min(q0 + s, p.nq - 1);
+        const cptr<S> m = MO + 9 * q;   // x, y, xx, xy, yy, ...
+        mx[s] = m[0]; my[s] = m[1]; mxx[s] = m[2]; mxy[s] = m[3]; myy[s] = m[4];
+        wq[s] = DELTA ? (S)1 : (S)W[q];
+    }
 #pragma unroll
-        for (int k = 0; k < 6; k++) ec[k] = sh.ecoef[k * plane + c];
-        const S cc = sh.ecoef[6 * plane + c];
+    for (int k = 0; k < FillSlots<S>::N; k++) {
+        if (!f.use[k]) continue;
 #pragma unroll
         for (int s = 0; s < QS; s++) {
-            if (s >= nqs) break;
-            const int q = q0 + s;
-            const cptr<S> m = MO + 9 * q;   // x, y, xx, xy, yy, ...
-            S e = ec[0];
-            e = fmaS(m[0], ec[1], e);
-            e = fmaS(m[1], ec[2], e);
-            e = fmaS(m[2], ec[3], e);
-            e = fmaS(m[3], ec[4], e);
-            e = fmaS(m[4], ec[5], e);
-            // ec and cc are zero outside the domain
-            sh.planes[s * plane + c] = fmaS(cc, xv[s], DELTA ? e : (S)W[q] * e);
+            S e = f.ec[k][0];
+            e = fmaS(mx[s], f.ec[k][1], e);
+            e = fmaS(my[s], f.ec[k][2], e);
+            e = fmaS(mxx[s], f.ec[k][3], e);
+            e = fmaS(mxy[s], f.ec[k][4], e);
+            e = fmaS(myy[s], f.ec[k][5], e);
+            // ec and cc are zero outside the domain; planes past nqs are never read
+            sh.planes[s * plane + threadIdx.x + k * blockDim.x] = fmaS(f.cc[k], v.x[k][s], DELTA ? e : wq[s] * e);
         }
     }
+    (void)nqs;
 }
 
 // Interface values of one velocity at the faces the thread's cell is upwind
@@ -305,6 +335,18 @@ __device__ __forceinline__ void owned_faces(const RingCell<S> &r, const Deriv<S>
     }
 }
 
+// The same for a velocity with both components non-zero: one expansion per
+// axis, to the east (xpos) or west face and to the north (ypos) or south face.
+template <class S>
+__device__ __forceinline__ void owned_faces_nz(const RingCell<S> &r, const Deriv<S> &d, bool xpos, bool ypos, S xh,
+                                               S yh, S kappa, S &vx, S &vy)
+{
+    const S hx = xpos ? r.hxe : r.hxw;
+    const S hy = ypos ? r.hyn : r.hys;
+    vx = r.active ? expand(d, hx - xh, -yh, kappa) : (S)0;
+    vy = r.active ? expand(d, -xh, hy - yh, kappa) : (S)0;
+}
+
 // ---------------------------------------------------------------------------
 // lq_faces: partial interface moments of a q-chunk.
 // ---------------------------------------------------------------------------
@@ -326,48 +368,102 @@ __device__ void lq_faces_body(const SweepParams &p, const LQStage &a, int tile, 
     // domain-boundary faces of the cell (diffuse-wall numerators)
     const bool wallW = r.wW, wallE = r.wE, wallS = r.wS, wallN = r.wN;
 
-    lq_prepare<S, DELTA>(p, a, sh, i0, j0);
+    const FillSlots<S> fsl = lq_prepare<S, DELTA>(p, a, i0, j0);
     double acc[4][4];   // faces W, E, S, N x (sum m x, sum m xi x, sum m eta x, diffuse numerator)
 #pragma unroll
     for (int f = 0; f < 4; f++)
 #pragma unroll
         for (int k = 0; k < 4; k++) acc[f][k] = 0.0;
-    for (int qa = q0; qa < q1; qa += QS) {
-        const int nqs = min(QS, q1 - qa);
-        __syncthreads();
-        lq_fill<S, DELTA>(p, a, sh, i0, j0, qa, nqs);
-        __syncthreads();
+    FillLoads<S, DELTA> ld;
+    lq_load<S, DELTA>(p, a, fsl, q0, min(QS, q1 - q0), ld);
+    // one group of QS velocities; FULL: all QS exist (no per-velocity checks)
+    auto group = [&](auto full, int qa, int nqs) {
+        constexpr bool FULL = decltype(full)::value;
+        int sgv[QS];
+        S xh[QS], yh[QS];
+        double w0[QS], w1[QS], w2[QS], xq[QS], yq[QS];
 #pragma unroll
         for (int s = 0; s < QS; s++) {
-            if (s >= nqs) break;
-            const int q = qa + s;
-            const cptr<S> mo = MO + 9 * q;
-            const int sg = SG[q];
+            const int q = min(qa + s, p.nq - 1);
+            sgv[s] = SG[q];
+            xh[s] = MO[9 * q] * hs;
+            yh[s] = MO[9 * q + 1] * hs;
+            w0[s] = WM[3 * q]; w1[s] = WM[3 * q + 1]; w2[s] = WM[3 * q + 2];
+            xq[s] = XI[q]; yq[s] = ETA[q];
+        }
+        __syncthreads();
+        lq_store<S, DELTA>(p, sh, fsl, qa, nqs, ld);
+        __syncthreads();
+        if (qa + QS < q1) lq_load<S, DELTA>(p, a, fsl, qa + QS, min(QS, q1 - qa - QS), ld);
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            if (!FULL && s >= nqs) break;
+            const int sg = sgv[s];
             const Deriv<S> d = derivs<S>(r, sh.planes + s * plane, HX2);
             S fv[4];
-            owned_faces<S>(r, d, sg, mo[0] * hs, mo[1] * hs, kappa, fv);
-            const cptr<double> m = WM + 3 * q;
-            const double m0 = m[0], mx = m[1], my = m[2];
-            // moments of the faces this cell computed for this velocity
-            auto add = [&](int f) {
+            owned_faces<S>(r, d, sg, xh[s], yh[s], kappa, fv);
+            // moments of the faces (zero for faces another cell computes)
+#pragma unroll
+            for (int f = 0; f < 4; f++) {
                 const double v = (double)fv[f];
-                acc[f][0] = __builtin_fma(m0, v, acc[f][0]);
-                acc[f][1] = __builtin_fma(mx, v, acc[f][1]);
-                acc[f][2] = __builtin_fma(my, v, acc[f][2]);
-            };
-            if (sg & 1) add(1);
-            else if (sg & 2) add(0);
-            else { add(0); add(1); }
-            if (sg & 4) add(3);
-            else if (sg & 8) add(2);
-            else { add(2); add(3); }
+                acc[f][0] = __builtin_fma(w0[s], v, acc[f][0]);
+                acc[f][1] = __builtin_fma(w1[s], v, acc[f][1]);
+                acc[f][2] = __builtin_fma(w2[s], v, acc[f][2]);
+            }
             // arriving at a wall: sum of |xi.n| m fbar (eq. of the diffuse-scattering rule)
-            const double xq = XI[q], yq = ETA[q];
-            if (wallW && (sg & 2)) acc[0][3] = __builtin_fma(-xq * m0, (double)fv[0], acc[0][3]);
-            if (wallE && (sg & 1)) acc[1][3] = __builtin_fma(xq * m0, (double)fv[1], acc[1][3]);
-            if (wallS && (sg & 8)) acc[2][3] = __builtin_fma(-yq * m0, (double)fv[2], acc[2][3]);
-            if (wallN && (sg & 4)) acc[3][3] = __builtin_fma(yq * m0, (double)fv[3], acc[3][3]);
+            if (wallW && (sg & 2)) acc[0][3] = __builtin_fma(-xq[s] * w0[s], (double)fv[0], acc[0][3]);
+            if (wallE && (sg & 1)) acc[1][3] = __builtin_fma(xq[s] * w0[s], (double)fv[1], acc[1][3]);
+            if (wallS && (sg & 8)) acc[2][3] = __builtin_fma(-yq[s] * w0[s], (double)fv[2], acc[2][3]);
+            if (wallN && (sg & 4)) acc[3][3] = __builtin_fma(yq[s] * w0[s], (double)fv[3], acc[3][3]);
         }
+    };
+    // a whole group of velocities with no zero component (the common case):
+    // one expansion per axis, scalar-selected moment weights
+    auto group_nz = [&](int qa) {
+        int sgv[QS];
+        S xh[QS], yh[QS];
+        double w0[QS], w1[QS], w2[QS], xq[QS], yq[QS];
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            const int q = qa + s;
+            sgv[s] = SG[q];
+            xh[s] = MO[9 * q] * hs;
+            yh[s] = MO[9 * q + 1] * hs;
+            w0[s] = WM[3 * q]; w1[s] = WM[3 * q + 1]; w2[s] = WM[3 * q + 2];
+            xq[s] = XI[q]; yq[s] = ETA[q];
+        }
+        __syncthreads();
+        lq_store<S, DELTA>(p, sh, fsl, qa, QS, ld);
+        __syncthreads();
+        if (qa + QS < q1) lq_load<S, DELTA>(p, a, fsl, qa + QS, min(QS, q1 - qa - QS), ld);
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            const bool xp = sgv[s] & 1, yp = sgv[s] & 4;
+            const Deriv<S> d = derivs<S>(r, sh.planes + s * plane, HX2);
+            S vx, vy;
+            owned_faces_nz<S>(r, d, xp, yp, xh[s], yh[s], kappa, vx, vy);
+            const double dx = (double)vx, dy = (double)vy;
+            const int fx = xp ? 1 : 0, fy = yp ? 3 : 2;   // face each value belongs to
+            const double w[3] = {w0[s], w1[s], w2[s]};
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                acc[1][k] = __builtin_fma(fx == 1 ? w[k] : 0.0, dx, acc[1][k]);
+                acc[0][k] = __builtin_fma(fx == 0 ? w[k] : 0.0, dx, acc[0][k]);
+                acc[3][k] = __builtin_fma(fy == 3 ? w[k] : 0.0, dy, acc[3][k]);
+                acc[2][k] = __builtin_fma(fy == 2 ? w[k] : 0.0, dy, acc[2][k]);
+            }
+            // arriving at a wall: sum of |xi.n| m fbar (eq. of the diffuse-scattering rule)
+            if (wallW && !xp) acc[0][3] = __builtin_fma(-xq[s] * w0[s], dx, acc[0][3]);
+            if (wallE && xp) acc[1][3] = __builtin_fma(xq[s] * w0[s], dx, acc[1][3]);
+            if (wallS && !yp) acc[2][3] = __builtin_fma(-yq[s] * w0[s], dy, acc[2][3]);
+            if (wallN && yp) acc[3][3] = __builtin_fma(yq[s] * w0[s], dy, acc[3][3]);
+        }
+    };
+    const cptr<int> GF = as_const(p.lq_gnz);
+    for (int qa = q0; qa < q1; qa += QS) {
+        if (GF[qa / QS]) group_nz(qa);
+        else if (q1 - qa >= QS) group(std::true_type{}, qa, QS);
+        else group(std::false_type{}, qa, q1 - qa);
     }
     // combine the two sides of every face: the tile writes the west and south
     // faces of its interior cells (and the east / north domain faces)
@@ -478,7 +574,7 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int tile,
     const double dt = p.dt, h = a.h;
     const size_t cell = (size_t)r.j * p.nx + r.i;
 
-    lq_prepare<S, DELTA>(p, a, sh, i0, j0);
+    const FillSlots<S> fsl = lq_prepare<S, DELTA>(p, a, i0, j0);
 
     // per-cell data of interior threads
     S alpha[4] = {0, 0, 0, 0};
@@ -597,38 +693,52 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int tile,
     double m0 = 0, m1 = 0, m2 = 0;   // partial cell moments of the output
     S *xw = sh.xch, *xe = sh.xch + QS * NT, *ys = sh.xch + 2 * QS * NT, *yn = sh.xch + 3 * QS * NT;
 
-    for (int qa = q0; qa < q1; qa += QS) {
-        const int nqs = min(QS, q1 - qa);
+    FillLoads<S, DELTA> ld;
+    lq_load<S, DELTA>(p, a, fsl, q0, min(QS, q1 - q0), ld);
+    const size_t ocell = r.interior ? cell : 0;   // own-cell loads of other threads: a valid address
+    // one group of QS velocities; FULL: all QS exist (no per-velocity checks)
+    auto group = [&](auto full, int qa, int nqs) {
+        constexpr bool FULL = decltype(full)::value;
+        int sgv[QS];
+        S xh[QS], yh[QS];
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            const int q = min(qa + s, p.nq - 1);
+            sgv[s] = SG[q];
+            xh[s] = MO[9 * q] * hs;
+            yh[s] = MO[9 * q + 1] * hs;
+        }
         __syncthreads();
-        lq_fill<S, DELTA>(p, a, sh, i0, j0, qa, nqs);
+        lq_store<S, DELTA>(p, sh, fsl, qa, nqs, ld);
         __syncthreads();
+        if (qa + QS < q1) lq_load<S, DELTA>(p, a, fsl, qa + QS, min(QS, q1 - qa - QS), ld);
+        // own-cell values for the output, needed after the exchange
+        S xo[QS], fo[QS];
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            const size_t qo = (size_t)min(qa + s, p.nq - 1) * nn + ocell;
+            xo[s] = X[qo];
+            fo[s] = a.stage != 0 ? F[qo] : (S)0;
+        }
         // interface values of the faces this cell is upwind of
 #pragma unroll
         for (int s = 0; s < QS; s++) {
-            if (s >= nqs) break;
-            const int q = qa + s;
-            const cptr<S> mo = MO + 9 * q;
+            if (!FULL && s >= nqs) break;
             const Deriv<S> d = derivs<S>(r, sh.planes + s * plane, HX2);
             S fv[4];
-            owned_faces<S>(r, d, SG[q], mo[0] * hs, mo[1] * hs, kappa, fv);
+            owned_faces<S>(r, d, sgv[s], xh[s], yh[s], kappa, fv);
             xw[s * NT + t] = fv[0];
             xe[s * NT + t] = fv[1];
             ys[s * NT + t] = fv[2];
             yn[s * NT + t] = fv[3];
         }
         __syncthreads();
-        if (!r.interior) continue;
-        S xo[QS], fo[QS];
+        if (!r.interior) return;
 #pragma unroll
         for (int s = 0; s < QS; s++) {
-            xo[s] = s < nqs ? X[(size_t)(qa + s) * nn + cell] : (S)0;
-            fo[s] = (a.stage != 0 && s < nqs) ? F[(size_t)(qa + s) * nn + cell] : (S)0;
-        }
-#pragma unroll
-        for (int s = 0; s < QS; s++) {
-            if (s >= nqs) break;
+            if (!FULL && s >= nqs) break;
             const int q = qa + s;
-            const int sg = SG[q];
+            const int sg = sgv[s];
             const cptr<S> mo = MO + 9 * q;
             const int b = s * NT + t;
             // face value = contributions of the cells on both sides
@@ -660,6 +770,76 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int tile,
             m1 = __builtin_fma(w3[1], yd, m1);
             m2 = __builtin_fma(w3[2], yd, m2);
         }
+    };
+    // a whole group of velocities with no zero component: one interface value
+    // per axis and cell (exchange arrays xw and ys hold them)
+    auto group_nz = [&](int qa) {
+        int sgv[QS];
+        S xh[QS], yh[QS];
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            const int q = qa + s;
+            sgv[s] = SG[q];
+            xh[s] = MO[9 * q] * hs;
+            yh[s] = MO[9 * q + 1] * hs;
+        }
+        __syncthreads();
+        lq_store<S, DELTA>(p, sh, fsl, qa, QS, ld);
+        __syncthreads();
+        if (qa + QS < q1) lq_load<S, DELTA>(p, a, fsl, qa + QS, min(QS, q1 - qa - QS), ld);
+        S xo[QS], fo[QS];
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            const size_t qo = (size_t)(qa + s) * nn + ocell;
+            xo[s] = X[qo];
+            fo[s] = a.stage != 0 ? F[qo] : (S)0;
+        }
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            const Deriv<S> d = derivs<S>(r, sh.planes + s * plane, HX2);
+            S vx, vy;
+            owned_faces_nz<S>(r, d, sgv[s] & 1, sgv[s] & 4, xh[s], yh[s], kappa, vx, vy);
+            xw[s * NT + t] = vx;
+            ys[s * NT + t] = vy;
+        }
+        __syncthreads();
+        if (!r.interior) return;
+#pragma unroll
+        for (int s = 0; s < QS; s++) {
+            const int q = qa + s;
+            const int sg = sgv[s];
+            const cptr<S> mo = MO + 9 * q;
+            const int b = s * NT + t;
+            // the west face's value sits with the west cell if xi > 0, else with this cell
+            const int bx = (sg & 1) ? b - 1 : b, by = (sg & 4) ? b - TX : b;
+            S fw = xw[bx], fe = xw[bx + 1], fs = ys[by], fn = ys[by + TX];
+            // velocities leaving a diffuse wall: fbar = E(rho_w, u_w)
+            if (dsf[0] && (sg & 1)) fw = rws[0] * (S)WE[q] - r0s;
+            if (dsf[1] && (sg & 2)) fe = rws[1] * (S)WE[p.nq + q] - r0s;
+            if (dsf[2] && (sg & 4)) fs = rws[2] * (S)WE[2 * p.nq + q] - r0s;
+            if (dsf[3] && (sg & 8)) fn = rws[3] * (S)WE[3 * p.nq + q] - r0s;
+            const S La = fmaS(mo[0] * cx, fmaS(alpha[1], fe, -alpha[0] * fw),
+                              mo[1] * cy * fmaS(alpha[3], fn, -alpha[2] * fs));
+            S Mq = M[0];
+#pragma unroll
+            for (int k = 0; k < 9; k++) Mq = fmaS(mo[k], M[k + 1], Mq);
+            const S sq = DELTA ? (S)1 : (S)W[q];
+            S R = kx_own * xo[s];
+            if (a.stage != 0) R = fmaS(kf_own, fo[s], R);
+            const S y = fmaS(aL, La, fmaS(sq, Mq, R));
+            out[(size_t)q * nn + cell] = y;
+            const cptr<double> w3 = WM + 3 * q;
+            const double yd = (double)y;
+            m0 = __builtin_fma(w3[0], yd, m0);
+            m1 = __builtin_fma(w3[1], yd, m1);
+            m2 = __builtin_fma(w3[2], yd, m2);
+        }
+    };
+    const cptr<int> GF = as_const(p.lq_gnz);
+    for (int qa = q0; qa < q1; qa += QS) {
+        if (GF[qa / QS]) group_nz(qa);
+        else if (q1 - qa >= QS) group(std::true_type{}, qa, QS);
+        else group(std::false_type{}, qa, q1 - qa);
     }
     if (!r.interior) return;
     double *cp = a.cell_part + ((long long)chunk * n + cell) * 4;
@@ -815,7 +995,7 @@ size_t lq_smem_bytes(const SweepParams &p, bool delta)
     // thread) reuses the same space
     const size_t plane = (size_t)(p.tile_x + 2) * (p.tile_y + 2);
     const size_t nt = (size_t)p.tile_x * p.tile_y;
-    const size_t a = (delta ? 4 : 8) * (plane * (p.lq_qs + 7) + 4 * (size_t)p.lq_qs * nt);
+    const size_t a = (delta ? 4 : 8) * (plane * p.lq_qs + 4 * (size_t)p.lq_qs * nt);
     return std::max(a, 16 * 8 * nt);
 }
 
