@@ -32,6 +32,7 @@ struct dugks {
     // any-size velocity sets
     double *mom_state = nullptr, *mom_G = nullptr, *face_part = nullptr, *face_mom = nullptr,
            *cell_part = nullptr;
+    void *fxv = nullptr, *fyv = nullptr;   // interface values of a stage ([q][face])
     std::vector<void *> allocs;
     // timing
     std::vector<hipEvent_t> ev;   // pairs
@@ -65,8 +66,8 @@ struct dugks::Batch {
         std::vector<Shape> shapes;
     };
     std::vector<Group> groups;
-    int4 *lq_tiles = nullptr, *lq_faces = nullptr, *lq_cells = nullptr;
-    int nlq_tiles = 0, nlq_faces = 0, nlq_cells = 0, lq_threads = 0;
+    int4 *lq_tiles = nullptr, *lq_faces = nullptr, *lq_upd = nullptr, *lq_cells = nullptr;
+    int nlq_tiles = 0, nlq_faces = 0, nlq_upd = 0, nlq_cells = 0, lq_threads = 0;
     size_t lq_smem = 0;
     hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [parity][1 or 2 steps]
     std::vector<void *> allocs;
@@ -266,6 +267,26 @@ static int raise_fast_smem(int lat, bool delta, int tx, int ty, size_t smem)
         mx = smem;
     }
     return DUGKS_OK;
+}
+
+// arguments of one stage of the any-size kernels
+static LQStage lq_args(const dugks *h, int stage, const void *X, const void *F, void *out)
+{
+    LQStage a{};
+    a.X = X;
+    a.F = F;
+    a.out = out;
+    a.momX = stage == 0 ? h->mom_state : h->mom_G;
+    a.momF = stage == 0 ? nullptr : h->mom_state;
+    a.face_part = h->face_part;
+    a.face_mom = h->face_mom;
+    a.cell_part = h->cell_part;
+    a.mom_out = stage == 0 ? h->mom_G : h->mom_state;
+    a.h = stage == 0 ? h->h1 : h->h2;
+    a.stage = stage;
+    a.fxv = h->fxv;
+    a.fyv = h->fyv;
+    return a;
 }
 
 // one stage of a lattice instance: fast-kind tiles by the compile-time-shape
@@ -680,6 +701,14 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
             dugks_destroy(h);
             return rc;
         }
+        void *fx = nullptr, *fy = nullptr;
+        if ((rc = dalloc(h, &fx, h->elem * (size_t)nq * (d->nx + 1) * d->ny)) ||
+            (rc = dalloc(h, &fy, h->elem * (size_t)nq * d->nx * (d->ny + 1)))) {
+            dugks_destroy(h);
+            return rc;
+        }
+        h->fxv = fx;
+        h->fyv = fy;
         h->mom_state = (double *)a;
         h->mom_G = (double *)b;
         h->face_part = (double *)fp;
@@ -784,8 +813,7 @@ int dugks_step(dugks_t *h, int nsteps)
         if (h->lat) {
             HIPCHECK(lattice_stage(h, 0, X, nullptr, h->G));
         } else {
-            LQStage a{X, nullptr, h->G, h->mom_state, nullptr, h->face_part, h->face_mom,
-                      h->cell_part, h->mom_G, h->h1, 0};
+            LQStage a = lq_args(h, 0, X, nullptr, h->G);
             HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
         }
         if ((rc = record(h, KC_STAGE_A, false))) return rc;
@@ -795,8 +823,7 @@ int dugks_step(dugks_t *h, int nsteps)
         } else {
             // the moments of fhat(t_n) are read by the update and overwritten by
             // the cell reduction that follows it on the same stream
-            LQStage a{h->G, X, Y, h->mom_G, h->mom_state, h->face_part, h->face_mom,
-                      h->cell_part, h->mom_state, h->h2, 1};
+            LQStage a = lq_args(h, 1, h->G, X, Y);
             HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
         }
         if ((rc = record(h, KC_STAGE_C, false))) return rc;
@@ -986,10 +1013,8 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
             void *X = c->state[par], *Y = c->state[1 - par];
             io[(par * 2 + 0) * n + k] = StageIO{X, nullptr, c->G, c->coefA, c->h1};
             io[(par * 2 + 1) * n + k] = StageIO{c->G, X, Y, c->coefC, c->h2};
-            lq[(par * 2 + 0) * n + k] = LQStage{X, nullptr, c->G, c->mom_state, nullptr, c->face_part,
-                                                c->face_mom, c->cell_part, c->mom_G, c->h1, 0};
-            lq[(par * 2 + 1) * n + k] = LQStage{c->G, X, Y, c->mom_G, c->mom_state, c->face_part,
-                                                c->face_mom, c->cell_part, c->mom_state, c->h2, 1};
+            lq[(par * 2 + 0) * n + k] = lq_args(c, 0, X, nullptr, c->G);
+            lq[(par * 2 + 1) * n + k] = lq_args(c, 1, c->G, X, Y);
         }
     }
     if ((rc = batch_upload(b, P, &b->d_params)) || (rc = batch_upload(b, io, &b->d_io)) ||
@@ -1053,7 +1078,7 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
         b->groups.push_back(g);
     }
     {
-        std::vector<int4> tiles, faces, cells;
+        std::vector<int4> tiles, faces, upd, cells;
         for (int k = 0; k < n; k++) {
             dugks *c = b->inst[k];
             if (c->lat != 0) continue;
@@ -1071,12 +1096,15 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
             const long long nface = (long long)(p.nx + 1) * p.ny + (long long)p.nx * (p.ny + 1);
             for (long long f = 0; f < (nface + 255) / 256; f++) faces.push_back(make_int4(k, (int)f, 0, 0));
             for (long long f = 0; f < (p.ncell + 255) / 256; f++) cells.push_back(make_int4(k, (int)f, 0, 0));
+            for (int ch = 0; ch < p.lq_nchunk; ch++)
+                for (long long f = 0; f < (p.ncell + 255) / 256; f++) upd.push_back(make_int4(k, (int)f, ch, 0));
         }
         b->nlq_tiles = (int)tiles.size();
         b->nlq_faces = (int)faces.size();
         b->nlq_cells = (int)cells.size();
+        b->nlq_upd = (int)upd.size();
         if ((rc = batch_upload(b, tiles, &b->lq_tiles)) || (rc = batch_upload(b, faces, &b->lq_faces)) ||
-            (rc = batch_upload(b, cells, &b->lq_cells))) {
+            (rc = batch_upload(b, upd, &b->lq_upd)) || (rc = batch_upload(b, cells, &b->lq_cells))) {
             dugks_destroy(h);
             return rc;
         }
@@ -1123,7 +1151,8 @@ static int batch_enqueue_step(dugks *h, int par)
         if (b->nlq_tiles)
             HIPCHECK(launch_lq_stage_batched(b->delta, b->d_params, b->d_lq + (size_t)(par * 2 + stage) * n,
                                              b->lq_tiles, b->nlq_tiles, b->lq_faces, b->nlq_faces,
-                                             b->lq_cells, b->nlq_cells, b->lq_threads, b->lq_smem, h->stream));
+                                             b->lq_upd, b->nlq_upd, b->lq_cells, b->nlq_cells, b->lq_threads,
+                                             b->lq_smem, h->stream));
     }
     return DUGKS_OK;
 }
@@ -1181,8 +1210,7 @@ static int stage_a_from(dugks *h, const void *X)
         HIPCHECK(lattice_stage(h, 0, X, nullptr, h->G));
     } else {
         HIPCHECK(launch_state_moments(h->p, h->delta, X, h->mom_state, h->stream));
-        LQStage a{X, nullptr, h->G, h->mom_state, nullptr, h->face_part, h->face_mom,
-                  h->cell_part, h->mom_G, h->h1, 0};
+        LQStage a = lq_args(h, 0, X, nullptr, h->G);
         HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
     }
     return DUGKS_OK;
@@ -1195,8 +1223,7 @@ static int step_from(dugks *h, const void *X, void *Y)
     if (h->lat) {
         HIPCHECK(lattice_stage(h, 1, h->G, X, Y));
     } else {
-        LQStage a{h->G, X, Y, h->mom_G, h->mom_state, h->face_part, h->face_mom,
-                  h->cell_part, h->mom_state, h->h2, 1};
+        LQStage a = lq_args(h, 1, h->G, X, Y);
         HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
     }
     return DUGKS_OK;

@@ -90,6 +90,8 @@ struct LQStage {
     double *mom_out;        // [cell][4] cell moments of out
     double h;               // characteristic step of the stage
     int stage;              // 0: stage A, 1: stage C
+    void *fxv = nullptr;    // [q][(nx+1) ny] interface values of the x-faces (storage type)
+    void *fyv = nullptr;    // [q][nx (ny+1)] interface values of the y-faces
 };
 
 // Per-instance buffers of one stage of the lattice kernels (batched launches).
@@ -125,11 +127,12 @@ hipError_t launch_stage_batched(int stage, int lat, bool delta, const SweepParam
                                 const int4 *work_fast, int nfast, const int4 *work_gen, int ngen,
                                 int nthreads, size_t smem, hipStream_t s);
 // Any-size kernels over many instances: work items (instance, tile, chunk, 0) for
-// the two tile kernels and (instance, block, 0, 0) for the two reductions.
+// the face kernel, (instance, cell block, chunk, 0) for the update and
+// (instance, block, 0, 0) for the two reductions.
 hipError_t launch_lq_stage_batched(bool delta, const SweepParams *P, const LQStage *A,
                                    const int4 *work_tiles, int ntiles, const int4 *work_faces, int nfaces,
-                                   const int4 *work_cells, int ncells, int nthreads, size_t smem,
-                                   hipStream_t s);
+                                   const int4 *work_upd, int nupd, const int4 *work_cells, int ncells,
+                                   int nthreads, size_t smem, hipStream_t s);
 
 // Large velocity sets (sweep_large.hip).  part < 0: all four kernels of the stage.
 hipError_t launch_lq_stage(bool delta, const SweepParams &p, const LQStage &a, hipStream_t s, int part);

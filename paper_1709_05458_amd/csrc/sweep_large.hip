@@ -348,13 +348,18 @@ __device__ __forceinline__ void owned_faces_nz(const RingCell<S> &r, const Deriv
 }
 
 // ---------------------------------------------------------------------------
-// lq_faces: partial interface moments of a q-chunk.
+// lq_faces: interface values of a q-chunk (stored for lq_update) and their
+// partial interface moments.  Per group of QS velocities: B planes into LDS;
+// each thread's upwind faces into an exchange buffer; then every interior
+// thread sums the two sides of its west and south faces (and of the east /
+// north domain faces at walls).
 // ---------------------------------------------------------------------------
 template <class S, bool DELTA>
 __device__ void lq_faces_body(const SweepParams &p, const LQStage &a, int tile, int chunk)
 {
     const int TX = p.tile_x, TY = p.tile_y, HX2 = TX + 2;
     const int plane = HX2 * (TY + 2);
+    const int NT = TX * TY, t = threadIdx.x;
     LQShared<S> sh = lq_shared<S>(p);
     const int gx = (p.nx + TX - 3) / (TX - 2);
     const int i0 = (tile % gx) * (TX - 2), j0 = (tile / gx) * (TY - 2);
@@ -365,8 +370,21 @@ __device__ void lq_faces_body(const SweepParams &p, const LQStage &a, int tile, 
     const cptr<S> MO = mono_table<S>(p);
     const cptr<double> WM = as_const(p.lq_wm), XI = as_const(p.xi), ETA = as_const(p.eta);
     const cptr<int> SG = as_const(p.lq_sgn);
-    // domain-boundary faces of the cell (diffuse-wall numerators)
+    const cptr<int> GF = as_const(p.lq_gnz);
+    // domain-boundary faces of the cell
     const bool wallW = r.wW, wallE = r.wE, wallS = r.wS, wallN = r.wN;
+    S *xw = sh.xch, *xe = sh.xch + QS * NT, *ys = sh.xch + 2 * QS * NT, *yn = sh.xch + 3 * QS * NT;
+    S *__restrict__ FX = (S *)a.fxv;
+    S *__restrict__ FY = (S *)a.fyv;
+    const size_t nxf = (size_t)(p.nx + 1) * p.ny, nyf = (size_t)p.nx * (p.ny + 1);
+    // face indices of interior threads: W, E, S, N (x-face and y-face numbering)
+    size_t fid[4] = {0, 0, 0, 0};
+    if (r.interior) {
+        fid[0] = (size_t)xface_id(p, r.i, r.j);
+        fid[1] = (size_t)xface_id(p, r.i + 1, r.j);
+        fid[2] = (size_t)(yface_id(p, r.i, r.j) - (long long)nxf);
+        fid[3] = (size_t)(yface_id(p, r.i, r.j + 1) - (long long)nxf);
+    }
 
     const FillSlots<S> fsl = lq_prepare<S, DELTA>(p, a, i0, j0);
     double acc[4][4];   // faces W, E, S, N x (sum m x, sum m xi x, sum m eta x, diffuse numerator)
@@ -376,20 +394,40 @@ __device__ void lq_faces_body(const SweepParams &p, const LQStage &a, int tile, 
         for (int k = 0; k < 4; k++) acc[f][k] = 0.0;
     FillLoads<S, DELTA> ld;
     lq_load<S, DELTA>(p, a, fsl, q0, min(QS, q1 - q0), ld);
-    // one group of QS velocities; FULL: all QS exist (no per-velocity checks)
-    auto group = [&](auto full, int qa, int nqs) {
-        constexpr bool FULL = decltype(full)::value;
+
+    // interior threads: store the face values of one velocity and add their moments
+    auto finish = [&](int q, S fw, S fe, S fs, S fn, double w0, double w1, double w2, double xq, double yq) {
+        FX[(size_t)q * nxf + fid[0]] = fw;
+        FY[(size_t)q * nyf + fid[2]] = fs;
+        if (wallE) FX[(size_t)q * nxf + fid[1]] = fe;
+        if (wallN) FY[(size_t)q * nyf + fid[3]] = fn;
+        const double v[4] = {(double)fw, (double)fe, (double)fs, (double)fn};
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            if ((f == 1 && !wallE) || (f == 3 && !wallN)) continue;
+            acc[f][0] = __builtin_fma(w0, v[f], acc[f][0]);
+            acc[f][1] = __builtin_fma(w1, v[f], acc[f][1]);
+            acc[f][2] = __builtin_fma(w2, v[f], acc[f][2]);
+        }
+        // arriving at a wall: sum of |xi.n| m fbar (eq. of the diffuse-scattering rule)
+        if (wallW && xq < 0.0) acc[0][3] = __builtin_fma(-xq * w0, v[0], acc[0][3]);
+        if (wallE && xq > 0.0) acc[1][3] = __builtin_fma(xq * w0, v[1], acc[1][3]);
+        if (wallS && yq < 0.0) acc[2][3] = __builtin_fma(-yq * w0, v[2], acc[2][3]);
+        if (wallN && yq > 0.0) acc[3][3] = __builtin_fma(yq * w0, v[3], acc[3][3]);
+    };
+
+    // one group of QS velocities; NZ: all present and no zero component (one
+    // upwind face per axis); FULL: all present
+    auto group = [&](auto nz, auto full, int qa, int nqs) {
+        constexpr bool NZ = decltype(nz)::value, FULL = decltype(full)::value;
         int sgv[QS];
         S xh[QS], yh[QS];
-        double w0[QS], w1[QS], w2[QS], xq[QS], yq[QS];
 #pragma unroll
         for (int s = 0; s < QS; s++) {
             const int q = min(qa + s, p.nq - 1);
             sgv[s] = SG[q];
             xh[s] = MO[9 * q] * hs;
             yh[s] = MO[9 * q + 1] * hs;
-            w0[s] = WM[3 * q]; w1[s] = WM[3 * q + 1]; w2[s] = WM[3 * q + 2];
-            xq[s] = XI[q]; yq[s] = ETA[q];
         }
         __syncthreads();
         lq_store<S, DELTA>(p, sh, fsl, qa, nqs, ld);
@@ -398,102 +436,53 @@ __device__ void lq_faces_body(const SweepParams &p, const LQStage &a, int tile, 
 #pragma unroll
         for (int s = 0; s < QS; s++) {
             if (!FULL && s >= nqs) break;
-            const int sg = sgv[s];
             const Deriv<S> d = derivs<S>(r, sh.planes + s * plane, HX2);
-            S fv[4];
-            owned_faces<S>(r, d, sg, xh[s], yh[s], kappa, fv);
-            // moments of the faces (zero for faces another cell computes)
-#pragma unroll
-            for (int f = 0; f < 4; f++) {
-                const double v = (double)fv[f];
-                acc[f][0] = __builtin_fma(w0[s], v, acc[f][0]);
-                acc[f][1] = __builtin_fma(w1[s], v, acc[f][1]);
-                acc[f][2] = __builtin_fma(w2[s], v, acc[f][2]);
+            if (NZ) {
+                S vx, vy;
+                owned_faces_nz<S>(r, d, sgv[s] & 1, sgv[s] & 4, xh[s], yh[s], kappa, vx, vy);
+                xw[s * NT + t] = vx;
+                ys[s * NT + t] = vy;
+            } else {
+                S fv[4];
+                owned_faces<S>(r, d, sgv[s], xh[s], yh[s], kappa, fv);
+                xw[s * NT + t] = fv[0];
+                xe[s * NT + t] = fv[1];
+                ys[s * NT + t] = fv[2];
+                yn[s * NT + t] = fv[3];
             }
-            // arriving at a wall: sum of |xi.n| m fbar (eq. of the diffuse-scattering rule)
-            if (wallW && (sg & 2)) acc[0][3] = __builtin_fma(-xq[s] * w0[s], (double)fv[0], acc[0][3]);
-            if (wallE && (sg & 1)) acc[1][3] = __builtin_fma(xq[s] * w0[s], (double)fv[1], acc[1][3]);
-            if (wallS && (sg & 8)) acc[2][3] = __builtin_fma(-yq[s] * w0[s], (double)fv[2], acc[2][3]);
-            if (wallN && (sg & 4)) acc[3][3] = __builtin_fma(yq[s] * w0[s], (double)fv[3], acc[3][3]);
-        }
-    };
-    // a whole group of velocities with no zero component (the common case):
-    // one expansion per axis, scalar-selected moment weights
-    auto group_nz = [&](int qa) {
-        int sgv[QS];
-        S xh[QS], yh[QS];
-        double w0[QS], w1[QS], w2[QS], xq[QS], yq[QS];
-#pragma unroll
-        for (int s = 0; s < QS; s++) {
-            const int q = qa + s;
-            sgv[s] = SG[q];
-            xh[s] = MO[9 * q] * hs;
-            yh[s] = MO[9 * q + 1] * hs;
-            w0[s] = WM[3 * q]; w1[s] = WM[3 * q + 1]; w2[s] = WM[3 * q + 2];
-            xq[s] = XI[q]; yq[s] = ETA[q];
         }
         __syncthreads();
-        lq_store<S, DELTA>(p, sh, fsl, qa, QS, ld);
-        __syncthreads();
-        if (qa + QS < q1) lq_load<S, DELTA>(p, a, fsl, qa + QS, min(QS, q1 - qa - QS), ld);
+        if (!r.interior) return;
 #pragma unroll
         for (int s = 0; s < QS; s++) {
-            const bool xp = sgv[s] & 1, yp = sgv[s] & 4;
-            const Deriv<S> d = derivs<S>(r, sh.planes + s * plane, HX2);
-            S vx, vy;
-            owned_faces_nz<S>(r, d, xp, yp, xh[s], yh[s], kappa, vx, vy);
-            const double dx = (double)vx, dy = (double)vy;
-            const int fx = xp ? 1 : 0, fy = yp ? 3 : 2;   // face each value belongs to
-            const double w[3] = {w0[s], w1[s], w2[s]};
-#pragma unroll
-            for (int k = 0; k < 3; k++) {
-                acc[1][k] = __builtin_fma(fx == 1 ? w[k] : 0.0, dx, acc[1][k]);
-                acc[0][k] = __builtin_fma(fx == 0 ? w[k] : 0.0, dx, acc[0][k]);
-                acc[3][k] = __builtin_fma(fy == 3 ? w[k] : 0.0, dy, acc[3][k]);
-                acc[2][k] = __builtin_fma(fy == 2 ? w[k] : 0.0, dy, acc[2][k]);
+            if (!FULL && s >= nqs) break;
+            const int q = qa + s, sg = sgv[s], b = s * NT + t;
+            const cptr<double> m = WM + 3 * q;
+            S fw, fe, fs, fn;
+            if (NZ) {
+                const int bx = (sg & 1) ? b - 1 : b, by = (sg & 4) ? b - TX : b;
+                fw = xw[bx]; fe = xw[bx + 1]; fs = ys[by]; fn = ys[by + TX];
+            } else {
+                fw = xe[b - 1] + xw[b]; fe = xe[b] + xw[b + 1];
+                fs = yn[b - TX] + ys[b]; fn = yn[b] + ys[b + TX];
             }
-            // arriving at a wall: sum of |xi.n| m fbar (eq. of the diffuse-scattering rule)
-            if (wallW && !xp) acc[0][3] = __builtin_fma(-xq[s] * w0[s], dx, acc[0][3]);
-            if (wallE && xp) acc[1][3] = __builtin_fma(xq[s] * w0[s], dx, acc[1][3]);
-            if (wallS && !yp) acc[2][3] = __builtin_fma(-yq[s] * w0[s], dy, acc[2][3]);
-            if (wallN && yp) acc[3][3] = __builtin_fma(yq[s] * w0[s], dy, acc[3][3]);
+            finish(q, fw, fe, fs, fn, m[0], m[1], m[2], XI[q], ETA[q]);
         }
     };
-    const cptr<int> GF = as_const(p.lq_gnz);
     for (int qa = q0; qa < q1; qa += QS) {
-        if (GF[qa / QS]) group_nz(qa);
-        else if (q1 - qa >= QS) group(std::true_type{}, qa, QS);
-        else group(std::false_type{}, qa, q1 - qa);
+        if (GF[qa / QS]) group(std::true_type{}, std::true_type{}, qa, QS);
+        else if (q1 - qa >= QS) group(std::false_type{}, std::true_type{}, qa, QS);
+        else group(std::false_type{}, std::false_type{}, qa, q1 - qa);
     }
-    // combine the two sides of every face: the tile writes the west and south
-    // faces of its interior cells (and the east / north domain faces)
-    __syncthreads();
-    double *xa = reinterpret_cast<double *>(sh.planes);   // [16][TX*TY], fits the plane area
-    const int NT = TX * TY, t = threadIdx.x;
-#pragma unroll
-    for (int f = 0; f < 4; f++)
-#pragma unroll
-        for (int k = 0; k < 4; k++) xa[(f * 4 + k) * NT + t] = acc[f][k];
-    __syncthreads();
     if (!r.interior) return;
-    const long long nface = (long long)(p.nx + 1) * p.ny + (long long)p.nx * (p.ny + 1);
+    const long long nface = (long long)nxf + (long long)nyf;
     double *part = a.face_part + (long long)chunk * nface * 4;
-    const int tl = t - 1, tb = t - TX;   // west and south neighbours
-    const long long fw = xface_id(p, r.i, r.j), fs = yface_id(p, r.i, r.j);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        part[4 * fw + k] = acc[0][k] + xa[(1 * 4 + k) * NT + tl];
-        part[4 * fs + k] = acc[2][k] + xa[(3 * 4 + k) * NT + tb];
-    }
-    if (wallE) {
-        const long long fe = xface_id(p, r.i + 1, r.j);
-#pragma unroll
-        for (int k = 0; k < 4; k++) part[4 * fe + k] = acc[1][k];
-    }
-    if (wallN) {
-        const long long fn = yface_id(p, r.i, r.j + 1);
-#pragma unroll
-        for (int k = 0; k < 4; k++) part[4 * fn + k] = acc[3][k];
+        part[4 * fid[0] + k] = acc[0][k];
+        part[4 * (nxf + fid[2]) + k] = acc[2][k];
+        if (wallE) part[4 * fid[1] + k] = acc[1][k];
+        if (wallN) part[4 * (nxf + fid[3]) + k] = acc[3][k];
     }
 }
 
@@ -551,43 +540,30 @@ __device__ void lq_face_reduce_body(const SweepParams &p, const LQStage &a, bool
 }
 
 // ---------------------------------------------------------------------------
-// lq_update: recovery, micro-flux and stage output of a q-chunk.  The part of
-// the micro-flux linear in the interface values is formed from the values the
-// upwind cells computed (exchanged through LDS); the equilibrium part of the
-// recovered interface values (eq. recover2f) and every equilibrium term of the
-// output are one cubic polynomial in xi per cell, built once.
+// lq_update: recovery, micro-flux and stage output of a q-chunk, one thread
+// per cell.  The interface values come from lq_faces; the equilibrium part of
+// the recovered interface values (eq. recover2f) and every equilibrium term of
+// the output are one cubic polynomial in xi per cell, built once.
 // ---------------------------------------------------------------------------
 template <class S, bool DELTA>
-__device__ void lq_update_body(const SweepParams &p, const LQStage &a, int tile, int chunk)
+__device__ void lq_update_body(const SweepParams &p, const LQStage &a, int block, int chunk)
 {
-    const int TX = p.tile_x, TY = p.tile_y, HX2 = TX + 2;
-    const int plane = HX2 * (TY + 2);
-    constexpr int QS = lq_group<DELTA>();
-    const int NT = TX * TY, t = threadIdx.x;
-    LQShared<S> sh = lq_shared<S>(p);
-    const int gx = (p.nx + TX - 3) / (TX - 2);
-    const int i0 = (tile % gx) * (TX - 2), j0 = (tile / gx) * (TY - 2);
+    const long long cell = (long long)block * blockDim.x + threadIdx.x;
+    if (cell >= p.ncell) return;
+    const int i = (int)(cell % p.nx), j = (int)(cell / p.nx);
     const int q0 = chunk * p.lq_chunk, q1 = min(p.nq, q0 + p.lq_chunk);
-    const long long n = p.ncell;
-    const RingCell<S> r = ring_cell<S>(p, i0, j0);
-    const S kappa = (S)p.kappa;
     const double dt = p.dt, h = a.h;
-    const size_t cell = (size_t)r.j * p.nx + r.i;
+    const size_t nxf = (size_t)(p.nx + 1) * p.ny, nyf = (size_t)p.nx * (p.ny + 1);
+    const long long fidl[4] = {xface_id(p, i, j), xface_id(p, i + 1, j), yface_id(p, i, j), yface_id(p, i, j + 1)};
+    const size_t fxw = (size_t)fidl[0], fxe = (size_t)fidl[1];
+    const size_t fys = (size_t)(fidl[2] - (long long)nxf), fyn = (size_t)(fidl[3] - (long long)nxf);
 
-    const FillSlots<S> fsl = lq_prepare<S, DELTA>(p, a, i0, j0);
-
-    // per-cell data of interior threads
-    S alpha[4] = {0, 0, 0, 0};
-    S rws[4] = {0, 0, 0, 0};
-    bool dsf[4] = {false, false, false, false};
+    S alpha[4];
+    S rws[4];
+    bool dsf[4];
     S M[10];   // 1, x, y, xx, xy, yy, xxx, xxy, xyy, yyy
-    S kx_own = 0, kf_own = 0, aL = 0, cx = 0, cy = 0;
-#pragma unroll
-    for (int k = 0; k < 10; k++) M[k] = (S)0;
-    if (r.interior) {
-        const int i = r.i, j = r.j;
-        const long long fid[4] = {xface_id(p, i, j), xface_id(p, i + 1, j), yface_id(p, i, j),
-                                  yface_id(p, i, j + 1)};
+    S kx_own, kf_own = 0, aL, cx, cy;
+    {
         const double tau_o = p.tau_field ? p.tau[cell] : p.tau0;
         double tb[4] = {tau_o, tau_o, tau_o, tau_o};
         if (p.tau_field) {
@@ -600,11 +576,10 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int tile,
             tb[2] = 0.5 * (tau_o + p.tau[(long long)jm * p.nx + i]);
             tb[3] = 0.5 * (tau_o + p.tau[(long long)jp * p.nx + i]);
         }
-        double be[4];
-        EPoly ef[4];
+        double be[4], pe[4][6];
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            const double *fm = a.face_mom + 8 * fid[k];
+            const double *fm = a.face_mom + 8 * fidl[k];
             double al;
             if (p.tau_field) {
                 al = 2.0 * tb[k] / (2.0 * tb[k] + h);
@@ -613,7 +588,9 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int tile,
                 al = p.uc.alpha[a.stage];
                 be[k] = p.uc.beta[a.stage];
             }
-            ef[k] = epoly(fm[0], fm[1], fm[2], fm[3], p.iRT, 1.0, DELTA);
+            const EPoly e = epoly(fm[0], fm[1], fm[2], fm[3], p.iRT, 1.0, DELTA);
+            pe[k][0] = e.c0; pe[k][1] = e.c1x; pe[k][2] = e.c1y;
+            pe[k][3] = e.c2xx; pe[k][4] = e.c2xy; pe[k][5] = e.c2yy;
             alpha[k] = (S)al;
             rws[k] = (S)fm[4];
         }
@@ -658,12 +635,6 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int tile,
         aL = (S)aLd;
         // equilibrium part of L: -(xi/dx)(beta_e E_e - beta_w E_w) - (eta/dy)(beta_n E_n - beta_s E_s)
         const double kx = -idx * aLd, ky = -idy * aLd;
-        double pe[4][6];
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            pe[k][0] = ef[k].c0; pe[k][1] = ef[k].c1x; pe[k][2] = ef[k].c1y;
-            pe[k][3] = ef[k].c2xx; pe[k][4] = ef[k].c2xy; pe[k][5] = ef[k].c2yy;
-        }
         double A[6], B[6];
 #pragma unroll
         for (int c = 0; c < 6; c++) {
@@ -684,165 +655,57 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int tile,
     const S r0s = (S)(DELTA ? p.rho0 : 0.0);
     const S *__restrict__ X = (const S *)a.X;
     const S *__restrict__ F = (const S *)a.F;
+    const S *__restrict__ FX = (const S *)a.fxv;
+    const S *__restrict__ FY = (const S *)a.fyv;
     S *__restrict__ out = (S *)a.out;
     const cptr<S> MO = mono_table<S>(p);
     const cptr<double> WM = as_const(p.lq_wm), W = as_const(p.w), WE = as_const(p.wall_E);
     const cptr<int> SG = as_const(p.lq_sgn);
-    const S hs = (S)h;
-    const size_t nn = (size_t)n;
+    const size_t n = (size_t)p.ncell;
     double m0 = 0, m1 = 0, m2 = 0;   // partial cell moments of the output
-    S *xw = sh.xch, *xe = sh.xch + QS * NT, *ys = sh.xch + 2 * QS * NT, *yn = sh.xch + 3 * QS * NT;
-
-    FillLoads<S, DELTA> ld;
-    lq_load<S, DELTA>(p, a, fsl, q0, min(QS, q1 - q0), ld);
-    const size_t ocell = r.interior ? cell : 0;   // own-cell loads of other threads: a valid address
-    // one group of QS velocities; FULL: all QS exist (no per-velocity checks)
-    auto group = [&](auto full, int qa, int nqs) {
-        constexpr bool FULL = decltype(full)::value;
-        int sgv[QS];
-        S xh[QS], yh[QS];
+    constexpr int U = 4;             // velocities whose loads are issued together
+    for (int qa = q0; qa < q1; qa += U) {
+        S fw[U], fe[U], fs[U], fn[U], xo[U], fo[U];
 #pragma unroll
-        for (int s = 0; s < QS; s++) {
-            const int q = min(qa + s, p.nq - 1);
-            sgv[s] = SG[q];
-            xh[s] = MO[9 * q] * hs;
-            yh[s] = MO[9 * q + 1] * hs;
+        for (int u = 0; u < U; u++) {
+            const size_t q = (size_t)min(qa + u, q1 - 1);
+            fw[u] = FX[q * nxf + fxw];
+            fe[u] = FX[q * nxf + fxe];
+            fs[u] = FY[q * nyf + fys];
+            fn[u] = FY[q * nyf + fyn];
+            xo[u] = X[q * n + cell];
+            fo[u] = a.stage != 0 ? F[q * n + cell] : (S)0;
         }
-        __syncthreads();
-        lq_store<S, DELTA>(p, sh, fsl, qa, nqs, ld);
-        __syncthreads();
-        if (qa + QS < q1) lq_load<S, DELTA>(p, a, fsl, qa + QS, min(QS, q1 - qa - QS), ld);
-        // own-cell values for the output, needed after the exchange
-        S xo[QS], fo[QS];
 #pragma unroll
-        for (int s = 0; s < QS; s++) {
-            const size_t qo = (size_t)min(qa + s, p.nq - 1) * nn + ocell;
-            xo[s] = X[qo];
-            fo[s] = a.stage != 0 ? F[qo] : (S)0;
-        }
-        // interface values of the faces this cell is upwind of
-#pragma unroll
-        for (int s = 0; s < QS; s++) {
-            if (!FULL && s >= nqs) break;
-            const Deriv<S> d = derivs<S>(r, sh.planes + s * plane, HX2);
-            S fv[4];
-            owned_faces<S>(r, d, sgv[s], xh[s], yh[s], kappa, fv);
-            xw[s * NT + t] = fv[0];
-            xe[s * NT + t] = fv[1];
-            ys[s * NT + t] = fv[2];
-            yn[s * NT + t] = fv[3];
-        }
-        __syncthreads();
-        if (!r.interior) return;
-#pragma unroll
-        for (int s = 0; s < QS; s++) {
-            if (!FULL && s >= nqs) break;
-            const int q = qa + s;
-            const int sg = sgv[s];
+        for (int u = 0; u < U; u++) {
+            const int q = qa + u;
+            if (q >= q1) break;
+            const int sg = SG[q];
             const cptr<S> mo = MO + 9 * q;
-            const int b = s * NT + t;
-            // face value = contributions of the cells on both sides
-            S fw, fe, fs, fn;
-            if (sg & 1) { fw = xe[b - 1]; fe = xe[b]; }
-            else if (sg & 2) { fw = xw[b]; fe = xw[b + 1]; }
-            else { fw = xe[b - 1] + xw[b]; fe = xe[b] + xw[b + 1]; }
-            if (sg & 4) { fs = yn[b - TX]; fn = yn[b]; }
-            else if (sg & 8) { fs = ys[b]; fn = ys[b + TX]; }
-            else { fs = yn[b - TX] + ys[b]; fn = yn[b] + ys[b + TX]; }
+            S w_ = fw[u], e_ = fe[u], s_ = fs[u], n_ = fn[u];
             // velocities leaving a diffuse wall: fbar = E(rho_w, u_w)
-            if (dsf[0] && (sg & 1)) fw = rws[0] * (S)WE[q] - r0s;
-            if (dsf[1] && (sg & 2)) fe = rws[1] * (S)WE[p.nq + q] - r0s;
-            if (dsf[2] && (sg & 4)) fs = rws[2] * (S)WE[2 * p.nq + q] - r0s;
-            if (dsf[3] && (sg & 8)) fn = rws[3] * (S)WE[3 * p.nq + q] - r0s;
-            const S La = fmaS(mo[0] * cx, fmaS(alpha[1], fe, -alpha[0] * fw),
-                              mo[1] * cy * fmaS(alpha[3], fn, -alpha[2] * fs));
+            if (dsf[0] && (sg & 1)) w_ = rws[0] * (S)WE[q] - r0s;
+            if (dsf[1] && (sg & 2)) e_ = rws[1] * (S)WE[p.nq + q] - r0s;
+            if (dsf[2] && (sg & 4)) s_ = rws[2] * (S)WE[2 * p.nq + q] - r0s;
+            if (dsf[3] && (sg & 8)) n_ = rws[3] * (S)WE[3 * p.nq + q] - r0s;
+            const S La = fmaS(mo[0] * cx, fmaS(alpha[1], e_, -alpha[0] * w_),
+                              mo[1] * cy * fmaS(alpha[3], n_, -alpha[2] * s_));
             S Mq = M[0];
 #pragma unroll
             for (int k = 0; k < 9; k++) Mq = fmaS(mo[k], M[k + 1], Mq);
             const S sq = DELTA ? (S)1 : (S)W[q];
-            S R = kx_own * xo[s];
-            if (a.stage != 0) R = fmaS(kf_own, fo[s], R);
+            S R = kx_own * xo[u];
+            if (a.stage != 0) R = fmaS(kf_own, fo[u], R);
             const S y = fmaS(aL, La, fmaS(sq, Mq, R));
-            out[(size_t)q * nn + cell] = y;
+            out[(size_t)q * n + cell] = y;
             const cptr<double> w3 = WM + 3 * q;
             const double yd = (double)y;
             m0 = __builtin_fma(w3[0], yd, m0);
             m1 = __builtin_fma(w3[1], yd, m1);
             m2 = __builtin_fma(w3[2], yd, m2);
         }
-    };
-    // a whole group of velocities with no zero component: one interface value
-    // per axis and cell (exchange arrays xw and ys hold them)
-    auto group_nz = [&](int qa) {
-        int sgv[QS];
-        S xh[QS], yh[QS];
-#pragma unroll
-        for (int s = 0; s < QS; s++) {
-            const int q = qa + s;
-            sgv[s] = SG[q];
-            xh[s] = MO[9 * q] * hs;
-            yh[s] = MO[9 * q + 1] * hs;
-        }
-        __syncthreads();
-        lq_store<S, DELTA>(p, sh, fsl, qa, QS, ld);
-        __syncthreads();
-        if (qa + QS < q1) lq_load<S, DELTA>(p, a, fsl, qa + QS, min(QS, q1 - qa - QS), ld);
-        S xo[QS], fo[QS];
-#pragma unroll
-        for (int s = 0; s < QS; s++) {
-            const size_t qo = (size_t)(qa + s) * nn + ocell;
-            xo[s] = X[qo];
-            fo[s] = a.stage != 0 ? F[qo] : (S)0;
-        }
-#pragma unroll
-        for (int s = 0; s < QS; s++) {
-            const Deriv<S> d = derivs<S>(r, sh.planes + s * plane, HX2);
-            S vx, vy;
-            owned_faces_nz<S>(r, d, sgv[s] & 1, sgv[s] & 4, xh[s], yh[s], kappa, vx, vy);
-            xw[s * NT + t] = vx;
-            ys[s * NT + t] = vy;
-        }
-        __syncthreads();
-        if (!r.interior) return;
-#pragma unroll
-        for (int s = 0; s < QS; s++) {
-            const int q = qa + s;
-            const int sg = sgv[s];
-            const cptr<S> mo = MO + 9 * q;
-            const int b = s * NT + t;
-            // the west face's value sits with the west cell if xi > 0, else with this cell
-            const int bx = (sg & 1) ? b - 1 : b, by = (sg & 4) ? b - TX : b;
-            S fw = xw[bx], fe = xw[bx + 1], fs = ys[by], fn = ys[by + TX];
-            // velocities leaving a diffuse wall: fbar = E(rho_w, u_w)
-            if (dsf[0] && (sg & 1)) fw = rws[0] * (S)WE[q] - r0s;
-            if (dsf[1] && (sg & 2)) fe = rws[1] * (S)WE[p.nq + q] - r0s;
-            if (dsf[2] && (sg & 4)) fs = rws[2] * (S)WE[2 * p.nq + q] - r0s;
-            if (dsf[3] && (sg & 8)) fn = rws[3] * (S)WE[3 * p.nq + q] - r0s;
-            const S La = fmaS(mo[0] * cx, fmaS(alpha[1], fe, -alpha[0] * fw),
-                              mo[1] * cy * fmaS(alpha[3], fn, -alpha[2] * fs));
-            S Mq = M[0];
-#pragma unroll
-            for (int k = 0; k < 9; k++) Mq = fmaS(mo[k], M[k + 1], Mq);
-            const S sq = DELTA ? (S)1 : (S)W[q];
-            S R = kx_own * xo[s];
-            if (a.stage != 0) R = fmaS(kf_own, fo[s], R);
-            const S y = fmaS(aL, La, fmaS(sq, Mq, R));
-            out[(size_t)q * nn + cell] = y;
-            const cptr<double> w3 = WM + 3 * q;
-            const double yd = (double)y;
-            m0 = __builtin_fma(w3[0], yd, m0);
-            m1 = __builtin_fma(w3[1], yd, m1);
-            m2 = __builtin_fma(w3[2], yd, m2);
-        }
-    };
-    const cptr<int> GF = as_const(p.lq_gnz);
-    for (int qa = q0; qa < q1; qa += QS) {
-        if (GF[qa / QS]) group_nz(qa);
-        else if (q1 - qa >= QS) group(std::true_type{}, qa, QS);
-        else group(std::false_type{}, qa, q1 - qa);
     }
-    if (!r.interior) return;
-    double *cp = a.cell_part + ((long long)chunk * n + cell) * 4;
+    double *cp = a.cell_part + ((long long)chunk * p.ncell + cell) * 4;
     cp[0] = m0; cp[1] = m1; cp[2] = m2; cp[3] = 0.0;
 }
 
@@ -913,8 +776,8 @@ __global__ void __launch_bounds__(256) lq_faces(const SweepParams p, const LQSta
 template <class S, bool DELTA>
 __global__ void __launch_bounds__(256) lq_update(const SweepParams p, const LQStage a)
 {
-    const int ntile = lq_ntile(p);
-    lq_update_body<S, DELTA>(p, a, blockIdx.x % ntile, blockIdx.x / ntile);
+    const int nblk = (int)((p.ncell + 255) / 256);
+    lq_update_body<S, DELTA>(p, a, blockIdx.x % nblk, blockIdx.x / nblk);
 }
 
 template <bool DELTA>
@@ -967,25 +830,25 @@ __global__ void __launch_bounds__(256) lq_cell_reduce_batched(const SweepParams 
 
 template <class S, bool DELTA>
 static hipError_t lq_batched_t(const SweepParams *P, const LQStage *A, const int4 *wt, int nt,
-                               const int4 *wf, int nf, const int4 *wc, int nc, int nthreads, size_t smem,
-                               hipStream_t s)
+                               const int4 *wf, int nf, const int4 *wu, int nu, const int4 *wc, int nc,
+                               int nthreads, size_t smem, hipStream_t s)
 {
     if (nt > 0) hipLaunchKernelGGL((lq_faces_batched<S, DELTA>), dim3(nt), dim3(nthreads), smem, s, P, A, wt);
     if (nf > 0) hipLaunchKernelGGL((lq_face_reduce_batched<DELTA>), dim3(nf), dim3(256), 0, s, P, A, wf);
-    if (nt > 0) hipLaunchKernelGGL((lq_update_batched<S, DELTA>), dim3(nt), dim3(nthreads), smem, s, P, A, wt);
+    if (nu > 0) hipLaunchKernelGGL((lq_update_batched<S, DELTA>), dim3(nu), dim3(256), 0, s, P, A, wu);
     if (nc > 0) hipLaunchKernelGGL((lq_cell_reduce_batched<DELTA>), dim3(nc), dim3(256), 0, s, P, A, wc);
     return hipGetLastError();
 }
 
 hipError_t launch_lq_stage_batched(bool delta, const SweepParams *P, const LQStage *A,
                                    const int4 *work_tiles, int ntiles, const int4 *work_faces, int nfaces,
-                                   const int4 *work_cells, int ncells, int nthreads, size_t smem,
-                                   hipStream_t s)
+                                   const int4 *work_upd, int nupd, const int4 *work_cells, int ncells,
+                                   int nthreads, size_t smem, hipStream_t s)
 {
-    return delta ? lq_batched_t<float, true>(P, A, work_tiles, ntiles, work_faces, nfaces, work_cells, ncells,
-                                             nthreads, smem, s)
-                 : lq_batched_t<double, false>(P, A, work_tiles, ntiles, work_faces, nfaces, work_cells,
-                                               ncells, nthreads, smem, s);
+    return delta ? lq_batched_t<float, true>(P, A, work_tiles, ntiles, work_faces, nfaces, work_upd, nupd,
+                                             work_cells, ncells, nthreads, smem, s)
+                 : lq_batched_t<double, false>(P, A, work_tiles, ntiles, work_faces, nfaces, work_upd, nupd,
+                                               work_cells, ncells, nthreads, smem, s);
 }
 
 size_t lq_smem_bytes(const SweepParams &p, bool delta)
@@ -1011,7 +874,8 @@ static hipError_t lq_stage_t(const SweepParams &p, const LQStage &a, hipStream_t
     if (part == 1 || part < 0)
         hipLaunchKernelGGL((lq_face_reduce<DELTA>), dim3((unsigned)((nface + 255) / 256)), dim3(256), 0, s, p, a);
     if (part == 2 || part < 0)
-        hipLaunchKernelGGL((lq_update<S, DELTA>), dim3(ntile * p.lq_nchunk), blk, smem, s, p, a);
+        hipLaunchKernelGGL((lq_update<S, DELTA>), dim3((unsigned)((p.ncell + 255) / 256) * p.lq_nchunk), dim3(256),
+                           0, s, p, a);
     if (part == 3 || part < 0)
         hipLaunchKernelGGL((lq_cell_reduce<DELTA>), dim3((unsigned)((p.ncell + 255) / 256)), dim3(256), 0, s, p, a);
     return hipGetLastError();
