@@ -516,7 +516,7 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
         const long long ntile = lq_ntile(p);
         int nch = (int)std::max(1LL, (2048 + ntile - 1) / ntile);
         nch = std::min(nch, std::max(1, nq / 16));
-        p.lq_qs = 4;
+        p.lq_qs = h->delta ? 4 : 2;
         p.lq_chunk = (nq + nch - 1) / nch;
         p.lq_chunk = (p.lq_chunk + p.lq_qs - 1) / p.lq_qs * p.lq_qs;   // whole plane groups
         p.lq_nchunk = (nq + p.lq_chunk - 1) / p.lq_chunk;

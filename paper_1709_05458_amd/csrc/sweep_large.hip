@@ -74,7 +74,7 @@ __device__ __forceinline__ cptr<double> mono_table<double>(const SweepParams &p)
 
 // Planes of B held in LDS at once (velocities per group).
 template <bool DELTA>
-constexpr int lq_group() { return DELTA ? 4 : 4; }
+constexpr int lq_group() { return DELTA ? 4 : 2; }
 
 // ---------------------------------------------------------------------------
 // Ring tiles.  A block of TX x TY threads covers the cells (i0-1 .. i0+TX-2) x
@@ -467,12 +467,13 @@ __device__ void lq_faces_body(const SweepParams &p, const LQStage &a, int tile, 
                 fs = yn[b - TX] + ys[b]; fn = yn[b] + ys[b + TX];
             }
             finish(q, fw, fe, fs, fn, m[0], m[1], m[2], XI[q], ETA[q]);
+            // one velocity at a time (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
         }
     };
     for (int qa = q0; qa < q1; qa += QS) {
         if (GF[qa / QS]) group(std::true_type{}, std::true_type{}, qa, QS);
-        else if (q1 - qa >= QS) group(std::false_type{}, std::true_type{}, qa, QS);
-        else group(std::false_type{}, std::false_type{}, qa, q1 - qa);
+        else group(std::false_type{}, std::false_type{}, qa, min(QS, q1 - qa));
     }
     if (!r.interior) return;
     const long long nface = (long long)nxf + (long long)nyf;
