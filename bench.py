@@ -109,6 +109,7 @@ def time_run(case, precision, steps, warmup, tile):
     from paper_1709_05458_amd import dugks
     s = dugks.Solver(case, precision, tile=tile)
     s.init_equilibrium(case.rho, case.ux, case.uy)
+    r0, ux0, uy0 = s.moments()
     s.step(warmup)
     s.sync()
     torch.cuda.synchronize()
@@ -127,9 +128,23 @@ def time_run(case, precision, steps, warmup, tile):
     r, ux, uy = s.moments()
     desc = s.describe()
     s.close()
+    # checks on the state after warmup + steps: conservation (periodic, moment-
+    # exact weights: exact up to rounding) and the viscous decay of the vortex
+    # against the analytic factor exp(-2 nu t) (the 1% initial noise decays faster)
+    t = (warmup + steps) * case.dt
+    mass0, mass = float(r0.sum()), float(r.sum())
+    mom0 = (float((r0 * ux0).sum()), float((r0 * uy0).sum()))
+    mom = (float((r * ux).sum()), float((r * uy).sum()))
+    from paper_1709_05458_amd import cases as C
+    _, uxa, uya = C.taylor_green_fields(case.grid.xc, case.grid.yc, t, case.meta["u0"], 1.0, 1.0,
+                                        case.meta["nu"], case.vs.RT)
+    err = math.sqrt(float(((ux - uxa) ** 2 + (uy - uya) ** 2).sum()) / float((uxa ** 2 + uya ** 2).sum()))
+    checks = {"steps_total": warmup + steps, "mass_rel_drift": abs(mass - mass0) / mass0,
+              "momentum_drift_over_mass": max(abs(mom[0] - mom0[0]), abs(mom[1] - mom0[1])) / mass0,
+              "u_rel_l2_vs_analytic_decay": err}
     return {"ms_per_step": ms_total / steps, "stage_a_ms": a_ms, "stage_c_ms": c_ms,
             "launches": (a_n, c_n), "variant": desc, "u_max": float(max(np.abs(ux).max(), np.abs(uy).max())),
-            "mass": float(r.mean())}
+            "mass": float(r.mean()), "checks": checks}
 
 
 def run_batched(args):
@@ -302,6 +317,7 @@ def main():
                      "bytes_per_launch": bytes_dom, "launch_ms": round(dom_ms, 5),
                      "stage_a_ms": round(r32["stage_a_ms"], 5), "stage_c_ms": round(r32["stage_c_ms"], 5)},
     }
+    out["checks"] = {"fp32_delta": r32["checks"], "fp64": r64["checks"] if r64 else None}
     if r64:
         g64 = pairs / (r64["ms_per_step"] * 1e-3) / 1e9
         a64 = 3 * 8 * pairs / (r64["stage_c_ms"] * 1e-3) / 1e9

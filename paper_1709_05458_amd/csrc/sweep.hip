@@ -342,7 +342,7 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
             if (STAGE == 0) {
                 // tilde f^+(t_n) = 5/4 fbar^{+,dt/6} - 1/4 fhat  (eq. f_tilde_1_3)
                 EPolyS<S> en;
-                en.set(ep_cell, 1.25 * e1);
+                en.set(ep_cell, 1.25 * e1 - rounding_of<S>(1.25 * c1 - 0.25));
                 const S kx = (S)(1.25 * c1 - 0.25);
                 [&]<int... qs>(std::integer_sequence<int, qs...>) {
                     ((t.R[qs] = fmaS(kx, v[qs],
@@ -371,8 +371,8 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
                     a_Ep = 0.75 * kw;
                 }
                 EPolyS<S> en, ep;
-                en.set(epoly(rn, drn, mxn, myn, p.iRT, cl, DELTA), a_En);
-                ep.set(ep_cell, a_Ep);
+                en.set(epoly(rn, drn, mxn, myn, p.iRT, cl, DELTA), a_En - rounding_of<S>(a_f));
+                ep.set(ep_cell, a_Ep - rounding_of<S>(a_G));
                 const S sf = (S)a_f, sg = (S)a_G;
                 [&]<int... qs>(std::integer_sequence<int, qs...>) {
                     ((t.R[qs] = fmaS(sf, fh[qs], fmaS(sg, v[qs],

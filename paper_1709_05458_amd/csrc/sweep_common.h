@@ -85,6 +85,17 @@ struct EPolyS {
     }
 };
 
+// Storage rounding of a constant update coefficient a: the kernels multiply
+// the own-cell distribution by (S)a, which in FP32 scales it by 1 + O(2^-24)
+// in the same direction every step, a drift that adds up over long runs.  The
+// equilibrium share of that error is taken back by adding -rounding_of<S>(a)
+// times the cell's equilibrium to the FP64 equilibrium terms (zero for FP64).
+template <class S>
+__device__ __forceinline__ double rounding_of(double a)
+{
+    return (double)(S)a - a;
+}
+
 // sum over the monomials e_x^a e_y^b (1 <= a + b <= 3) of the flux's
 // equilibrium part; evaluated with compile-time integer e.
 template <class S>

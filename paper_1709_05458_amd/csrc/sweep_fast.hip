@@ -228,7 +228,7 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
         const S kx = (S)(1.25 * c1 - 0.25);
 #pragma unroll
         for (int q = 0; q < Q; q++) R0[q] = kx * v[0][q];
-        const double k = 1.25 * e1;
+        const double k = 1.25 * e1 - rounding_of<S>(1.25 * c1 - 0.25);
         EO = {ep_own.c0 * k, ep_own.c1x * k, ep_own.c1y * k, ep_own.c2xx * k, ep_own.c2xy * k, ep_own.c2yy * k};
     } else {
         // fhat(t_{n+1}) = a_f fhat + a_G tilde f(t') + a_En E^n + a_Ep E' + 4dt/7 L**
@@ -266,6 +266,8 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
         double rn, drn, mxn, myn;
         phys_moments(p, DELTA, b0, bx, by, rn, drn, mxn, myn);
         const EPoly en = epoly(rn, drn, mxn, myn, p.iRT, cl, DELTA);
+        a_En -= rounding_of<S>(a_f);
+        a_Ep -= rounding_of<S>(a_G);
         EO = {a_En * en.c0 + a_Ep * ep_own.c0, a_En * en.c1x + a_Ep * ep_own.c1x,
               a_En * en.c1y + a_Ep * ep_own.c1y, a_En * en.c2xx + a_Ep * ep_own.c2xx,
               a_En * en.c2xy + a_Ep * ep_own.c2xy, a_En * en.c2yy + a_Ep * ep_own.c2yy};

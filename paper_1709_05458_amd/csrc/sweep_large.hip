@@ -610,7 +610,7 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int block
         double EO[6], aLd;
         if (a.stage == 0) {
             // tilde f^+(t_n) = (5/4 c1 - 1/4) fhat + 5/4 e1 E^n (eq. f_tilde_1_3)
-            const double k = 1.25 * e1;
+            const double k = 1.25 * e1 - rounding_of<S>(1.25 * c1 - 0.25);
             EO[0] = k * ex.c0; EO[1] = k * ex.c1x; EO[2] = k * ex.c1y;
             EO[3] = k * ex.c2xx; EO[4] = k * ex.c2xy; EO[5] = k * ex.c2yy;
             kx_own = (S)(1.25 * c1 - 0.25);
@@ -626,6 +626,8 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int block
             }
             const double *mf = a.momF + 4 * cell;
             const EPoly en = epoly(mf[0], mf[1], mf[2], mf[3], p.iRT, 1.0, DELTA);
+            a_En -= rounding_of<S>(a_f);
+            a_Ep -= rounding_of<S>(a_G);
             EO[0] = a_En * en.c0 + a_Ep * ex.c0; EO[1] = a_En * en.c1x + a_Ep * ex.c1x;
             EO[2] = a_En * en.c1y + a_Ep * ex.c1y; EO[3] = a_En * en.c2xx + a_Ep * ex.c2xx;
             EO[4] = a_En * en.c2xy + a_Ep * ex.c2xy; EO[5] = a_En * en.c2yy + a_Ep * ex.c2yy;
