@@ -310,7 +310,7 @@ def main():
         "config": {"workload": f"taylor-green {args.n}x{args.n} periodic, {case.vs.name}, FP32-delta storage, T3S3",
                    "cells": args.n * args.n, "velocities": Q, "pairs": pairs,
                    "variant": r32["variant"]},
-        "roofline": {"bound": "hbm", "kernel": f"stage {dom} (sweep_small, STAGE={1 if dom == 'C' else 0})",
+        "roofline": {"bound": "hbm", "kernel": f"stage {dom} (sweep_fast, STAGE={1 if dom == 'C' else 0})",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),

@@ -54,6 +54,7 @@ struct dugks::Batch {
     LQStage *d_lq = nullptr;        // [parity][stage][instance]
     struct Shape {                  // fast-kind tiles of one compiled tile shape
         int tx = 0, ty = 0;
+        bool tf = false;            // instances with a tau field
         int4 *work = nullptr;
         int n = 0;
     };
@@ -1027,8 +1028,9 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
         dugks::Batch::Group g;
         g.lat = lat;
         std::vector<int4> fast, gen;
-        std::vector<std::vector<int4>> by_shape(8);
-        std::vector<std::pair<int, int>> shape_of(8, {0, 0});
+        // one work list per compiled tile shape and tau kind (index 2 * shape + tau_field)
+        std::vector<std::vector<int4>> by_shape(16);
+        std::vector<std::pair<int, int>> shape_of(16, {0, 0});
         for (int k = 0; k < n; k++) {
             dugks *c = b->inst[k];
             if (c->lat != lat) continue;
@@ -1048,8 +1050,9 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
                                         (p.pery || (j0 >= 2 && j0 + p.tile_y <= p.ny - 2));
                     const int si = c->fast_ct ? fast_tile_index(p.tile_x, p.tile_y) : -1;
                     if (isfast && si >= 0) {
-                        by_shape[si].push_back(make_int4(k, tx, ty, 0));
-                        shape_of[si] = {p.tile_x, p.tile_y};
+                        const int slot = 2 * si + (p.tau_field ? 1 : 0);
+                        by_shape[slot].push_back(make_int4(k, tx, ty, 0));
+                        shape_of[slot] = {p.tile_x, p.tile_y};
                     } else {
                         (isfast ? fast : gen).push_back(make_int4(k, tx, ty, 0));
                     }
@@ -1062,11 +1065,12 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
             dugks_destroy(h);
             return rc;
         }
-        for (int si = 0; si < 8; si++) {
+        for (int si = 0; si < 16; si++) {
             if (by_shape[si].empty()) continue;
             dugks::Batch::Shape sh;
             sh.tx = shape_of[si].first;
             sh.ty = shape_of[si].second;
+            sh.tf = (si & 1) != 0;
             sh.n = (int)by_shape[si].size();
             if ((rc = raise_fast_smem(lat, b->delta, sh.tx, sh.ty, g.smem)) ||
                 (rc = batch_upload(b, by_shape[si], &sh.work))) {
@@ -1143,7 +1147,7 @@ static int batch_enqueue_step(dugks *h, int par)
         const StageIO *io = b->d_io + (size_t)(par * 2 + stage) * n;
         for (const auto &g : b->groups) {
             for (const auto &sh : g.shapes)
-                HIPCHECK(launch_stage_fast_batched(stage, g.lat, b->delta, sh.tx, sh.ty, b->d_params, io, sh.work,
+                HIPCHECK(launch_stage_fast_batched(stage, g.lat, b->delta, sh.tx, sh.ty, sh.tf, b->d_params, io, sh.work,
                                                    sh.n, g.smem, h->stream));
             HIPCHECK(launch_stage_batched(stage, g.lat, b->delta, b->d_params, io, g.fast, g.nfast, g.gen,
                                           g.ngen, g.nthreads, g.smem, h->stream));

@@ -119,7 +119,8 @@ int fast_tile_index(int tx, int ty);
 hipError_t set_fast_smem(int lat, bool delta, int tx, int ty, size_t bytes);
 hipError_t launch_stage_fast(int stage, int lat, bool delta, const SweepParams &p, double h, const void *X,
                              const void *F, void *out, const void *coef, hipStream_t s);
-hipError_t launch_stage_fast_batched(int stage, int lat, bool delta, int tx, int ty, const SweepParams *P,
+hipError_t launch_stage_fast_batched(int stage, int lat, bool delta, int tx, int ty, bool tau_field,
+                                     const SweepParams *P,
                                      const StageIO *io, const int4 *work, int nwork, size_t smem,
                                      hipStream_t s);
 // Many instances in one launch per tile kind: work items (instance, tile x, tile y, 0).

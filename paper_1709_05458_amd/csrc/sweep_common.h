@@ -43,20 +43,33 @@ struct EPoly {
     double c0, c1x, c1y, c2xx, c2xy, c2yy;
 };
 
-__device__ __forceinline__ EPoly epoly(double rho, double drho, double mx, double my,
-                                       double iRT_in, double clat, bool delta)
+// 1/x from the hardware estimate and two Newton steps (within an ulp of the
+// rounded quotient for the positive, normal densities it is used on)
+__device__ __forceinline__ double recip(double x)
 {
-    const double ir = 1.0 / rho, iRT = iRT_in;
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// (iRT and clat are uniform: their products are formed once per thread)
+__device__ __forceinline__ EPoly epoly(double rho, double drho, double mx, double my,
+                                       double iRT, double clat, bool delta)
+{
+    const double ir = recip(rho);
     const double ux = mx * ir, uy = my * ir;
-    const double uu = ux * ux + uy * uy;
+    const double uu = __builtin_fma(ux, ux, uy * uy);
+    const double c1 = iRT * clat, h2 = 0.5 * c1 * c1;
     EPoly e;
-    e.c0 = (delta ? drho : rho) - 0.5 * rho * uu * iRT;
-    e.c1x = mx * iRT * clat;
-    e.c1y = my * iRT * clat;
-    const double k2 = 0.5 * rho * iRT * iRT * clat * clat;
-    e.c2xx = k2 * ux * ux;
-    e.c2xy = 2.0 * k2 * ux * uy;
-    e.c2yy = k2 * uy * uy;
+    e.c0 = __builtin_fma(-(rho * (0.5 * iRT)), uu, delta ? drho : rho);
+    e.c1x = mx * c1;
+    e.c1y = my * c1;
+    const double kx = (rho * h2) * ux, ky = (rho * h2) * uy;
+    e.c2xx = kx * ux;
+    e.c2xy = (kx + kx) * uy;
+    e.c2yy = ky * uy;
     return e;
 }
 
@@ -82,6 +95,21 @@ struct EPolyS {
         if (EX && EY) v = fmaS((S)(EX * EY), c2xy, v);
         if (EY) v = fmaS((S)(EY * EY), c2yy, v);
         return v;
+    }
+    // values at e and at -e from one even (quadratic) and one odd (linear) part
+    template <int EX, int EY>
+    __device__ __forceinline__ void eval_pair(S &vp, S &vm) const
+    {
+        S ev = c0;
+        if (EX) ev = fmaS((S)(EX * EX), c2xx, ev);
+        if (EX && EY) ev = fmaS((S)(EX * EY), c2xy, ev);
+        if (EY) ev = fmaS((S)(EY * EY), c2yy, ev);
+        S od;
+        if (EX && EY) od = fmaS((S)EY, c1y, (S)EX * c1x);
+        else if (EX) od = (S)EX * c1x;
+        else od = (S)EY * c1y;
+        vp = ev + od;
+        vm = ev - od;
     }
 };
 

@@ -33,10 +33,10 @@ namespace dk {
 // weights of one velocity (uniform spacing; upwind choice, foot point and
 // 3-point derivatives folded into the weights), their moments in double,
 // and the linear flux part.
-template <class Lat, class S, bool DELTA, int q, int HX, int PL>
+template <class Lat, class S, bool DELTA, bool TF, int q, int HX, int PL>
 __device__ __forceinline__ void fast_faces(const SweepParams &p, const S *lds, const S *__restrict__ C,
                                            double (&mr)[4], double (&mx)[4], double (&my)[4], const S (&kxm)[4],
-                                           const S (&kym)[4], bool tfield, const S (&al)[4], S &La)
+                                           const S (&kym)[4], const S (&al)[4], S &La)
 {
     constexpr int EX = Lat::ex(q), EY = Lat::ey(q), SH = Lat::shell(q);
     const S *P = lds + q * PL;
@@ -79,12 +79,12 @@ __device__ __forceinline__ void fast_faces(const SweepParams &p, const S *lds, c
     S l = 0;
     if (EX) {
         const S kx = EX > 0 ? kxm[EX] : -kxm[-EX];
-        const S dxv = tfield ? fmaS(al[1], ve, -al[0] * vw) : ve - vw;
+        const S dxv = TF ? fmaS(al[1], ve, -al[0] * vw) : ve - vw;
         l = kx * dxv;
     }
     if (EY) {
         const S ky = EY > 0 ? kym[EY] : -kym[-EY];
-        const S dyv = tfield ? fmaS(al[3], vn, -al[2] * vs) : vn - vs;
+        const S dyv = TF ? fmaS(al[3], vn, -al[2] * vs) : vn - vs;
         l = fmaS(ky, dyv, l);
     }
     La = l;
@@ -92,7 +92,8 @@ __device__ __forceinline__ void fast_faces(const SweepParams &p, const S *lds, c
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <class Lat, class S, bool DELTA, int STAGE, int TX, int TY>
+// TF: per-cell relaxation times (a tau field) rather than one tau
+template <class Lat, class S, bool DELTA, bool TF, int STAGE, int TX, int TY>
 __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, const S *__restrict__ X,
                                           const S *__restrict__ F, S *__restrict__ out,
                                           const S *__restrict__ coef, int tx, int ty)
@@ -177,14 +178,14 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
     EPoly ep_own{};
     double rho_own = 1.0;
     const long long ocell = (long long)j * p.nx + i;
-    const double tau_o = (p.tau_field && valid) ? p.tau[ocell] : p.tau0;
+    const double tau_o = (TF && valid) ? p.tau[ocell] : p.tau0;
 #pragma unroll
     for (int s = 0; s < NS; s++) {
         double rho, drho, mxx, myy;
         phys_moments(p, DELTA, a0[s], ax[s], ay[s], rho, drho, mxx, myy);
         if (!has[s]) { rho = 1.0; drho = DELTA ? 0.0 : 1.0; mxx = myy = 0.0; }
         double cc, ce;
-        if (!p.tau_field) {
+        if (!TF) {
             cc = p.uc.cc[STAGE];
             ce = p.uc.ce[STAGE];
         } else {
@@ -203,14 +204,25 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
         ccs[s] = (S)cc;
     }
     {
+        // velocities q and opp(q) (e and -e) share the even part of E
         [&]<int... qs>(std::integer_sequence<int, qs...>) {
             (([&] {
-                 constexpr int EX = Lat::ex(qs), EY = Lat::ey(qs);
+                 constexpr int EX = Lat::ex(qs), EY = Lat::ey(qs), QO = Lat::opp(qs);
                  const S wqs = DELTA ? (S)1 : (S)p.wtab[Lat::shell(qs)][1];
+                 if constexpr (QO == qs) {
 #pragma unroll
-                 for (int s = 0; s < NS; s++) {
-                     const S e = eb[s].template eval<EX, EY>();
-                     lds[qs * PS + lpos[s]] = fmaS(ccs[s], v[s][qs], DELTA ? e : wqs * e);
+                     for (int s = 0; s < NS; s++) {
+                         const S e = eb[s].template eval<EX, EY>();
+                         lds[qs * PS + lpos[s]] = fmaS(ccs[s], v[s][qs], DELTA ? e : wqs * e);
+                     }
+                 } else if constexpr (QO > qs) {
+#pragma unroll
+                     for (int s = 0; s < NS; s++) {
+                         S ep, em;
+                         eb[s].template eval_pair<EX, EY>(ep, em);
+                         lds[qs * PS + lpos[s]] = fmaS(ccs[s], v[s][qs], DELTA ? ep : wqs * ep);
+                         lds[QO * PS + lpos[s]] = fmaS(ccs[s], v[s][QO], DELTA ? em : wqs * em);
+                     }
                  }
              }()),
              ...);
@@ -219,8 +231,8 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
     (void)rho_own;
 
     // ---- own cell: the part of the output that does not depend on the faces
-    const double c1 = p.tau_field ? (12.0 * tau_o - dt) / (12.0 * tau_o + 3.0 * dt) : p.uc.c1;
-    const double e1 = p.tau_field ? 4.0 * dt / (12.0 * tau_o + 3.0 * dt) : p.uc.e1;
+    const double c1 = TF ? (12.0 * tau_o - dt) / (12.0 * tau_o + 3.0 * dt) : p.uc.c1;
+    const double e1 = TF ? 4.0 * dt / (12.0 * tau_o + 3.0 * dt) : p.uc.e1;
     S R0[Q];
     EPoly EO;   // equilibrium terms of the output (storage units), before the flux part is added
     if (STAGE == 0) {
@@ -235,7 +247,7 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
         // (eqs. fhp, collisionterm, feqIntD3rdHat2_DS, with 3 dt/7 L* taken
         // from the T2 update of step 2)
         double a_f = p.uc.a_f, a_En = p.uc.a_En, a_G = p.uc.a_G, a_Ep = p.uc.a_Ep;
-        if (p.tau_field) {
+        if (TF) {
             const double kw = 6.0 * dt / (6.0 * tau_o + dt);
             a_f = (4.0 - 6.0 * c1) / 7.0;
             a_En = -6.0 / 7.0 * e1;
@@ -277,7 +289,7 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
 
     // ---- interface recovery weights (eq. recover2f) -------------------------
     double alpha[4], beta[4];
-    if (p.tau_field) {
+    if (TF) {
         const int im = i > 0 ? i - 1 : p.nx - 1, ip = i < p.nx - 1 ? i + 1 : 0;
         const int jm = j > 0 ? j - 1 : p.ny - 1, jp = j < p.ny - 1 ? j + 1 : 0;
         const double tb[4] = {0.5 * (tau_o + p.tau[(long long)j * p.nx + im]),
@@ -299,8 +311,8 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
     // multiples m * (-clat/dx) (times alpha when it is the same on all faces)
     S kxm[4], kym[4], al[4];
     {
-        const double fx = -cl * p.inv_dx * (p.tau_field ? 1.0 : alpha[0]);
-        const double fy = -cl * p.inv_dy * (p.tau_field ? 1.0 : alpha[0]);
+        const double fx = -cl * p.inv_dx * (TF ? 1.0 : alpha[0]);
+        const double fy = -cl * p.inv_dy * (TF ? 1.0 : alpha[0]);
 #pragma unroll
         for (int m = 0; m < 4; m++) {
             kxm[m] = (S)(m * fx);
@@ -314,9 +326,8 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
     S La[Q];
     {
         const S *base = lds + (ly + 2) * HX + (lx + 2);
-        const bool tf = p.tau_field;
         [&]<int... qs>(std::integer_sequence<int, qs...>) {
-            (fast_faces<Lat, S, DELTA, qs, HX, PS>(p, base, coef + qs * 24, mr, mx, my, kxm, kym, tf, al, La[qs]),
+            (fast_faces<Lat, S, DELTA, TF, qs, HX, PS>(p, base, coef + qs * 24, mr, mx, my, kxm, kym, al, La[qs]),
              ...);
         }(Seq{});
     }
@@ -347,49 +358,75 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
     const S aLs = (S)aL;
     const size_t no = (size_t)p.ncell_o;
     const unsigned oc = (unsigned)ocell;
+    // M at e and -e (velocities q and opp(q)) from its even (m0 and quadratic)
+    // and odd (linear and cubic) parts
+    auto store = [&](int q, S M, S wq) {
+        const S r = fmaS(aLs, La[q], R0[q]);
+        *(S *)((char *)(out + (size_t)q * no) + (unsigned)(sizeof(S) * oc)) = DELTA ? r + M : fmaS(wq, M, r);
+    };
     [&]<int... qs>(std::integer_sequence<int, qs...>) {
         (([&] {
-             constexpr int EX = Lat::ex(qs), EY = Lat::ey(qs);
-             S M = m0;
-             if (EX) M = fmaS((S)EX, m_x, M);
-             if (EY) M = fmaS((S)EY, m_y, M);
-             if (EX) M = fmaS((S)(EX * EX), m_xx, M);
-             if (EX && EY) M = fmaS((S)(EX * EY), m_xy, M);
-             if (EY) M = fmaS((S)(EY * EY), m_yy, M);
-             if (EX) M = fmaS((S)(EX * EX * EX), m_xxx, M);
-             if (EX && EY) M = fmaS((S)(EX * EX * EY), m_xxy, M);
-             if (EX && EY) M = fmaS((S)(EX * EY * EY), m_xyy, M);
-             if (EY) M = fmaS((S)(EY * EY * EY), m_yyy, M);
-             const S r = fmaS(aLs, La[qs], R0[qs]);
-             *(S *)((char *)(out + (size_t)qs * no) + (unsigned)(sizeof(S) * oc)) =
-                 DELTA ? r + M : fmaS((S)p.wtab[Lat::shell(qs)][1], M, r);
+             constexpr int EX = Lat::ex(qs), EY = Lat::ey(qs), QO = Lat::opp(qs);
+             const S wq = DELTA ? (S)1 : (S)p.wtab[Lat::shell(qs)][1];
+             if constexpr (QO == qs) {
+                 store(qs, m0, wq);
+             } else if constexpr (QO > qs) {
+                 S ev = m0;
+                 if (EX) ev = fmaS((S)(EX * EX), m_xx, ev);
+                 if (EX && EY) ev = fmaS((S)(EX * EY), m_xy, ev);
+                 if (EY) ev = fmaS((S)(EY * EY), m_yy, ev);
+                 S od = (S)0;
+                 bool first = true;
+                 auto term = [&](S k, S m) {
+                     od = first ? k * m : fmaS(k, m, od);
+                     first = false;
+                 };
+                 if (EX) term((S)EX, m_x);
+                 if (EY) term((S)EY, m_y);
+                 if (EX) term((S)(EX * EX * EX), m_xxx);
+                 if (EX && EY) term((S)(EX * EX * EY), m_xxy);
+                 if (EX && EY) term((S)(EX * EY * EY), m_xyy);
+                 if (EY) term((S)(EY * EY * EY), m_yyy);
+                 store(qs, ev + od, wq);
+                 store(QO, ev - od, wq);
+             }
          }()),
          ...);
     }(Seq{});
 }
 
-// at least two waves per SIMD (the LDS of the largest tiles allows two blocks per CU)
-template <class Lat, class S, bool DELTA, int STAGE, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2)))
+// Waves per SIMD the register budget is cut for: two where the tile's LDS lets
+// two blocks share a CU, else one (FP64 D2Q37: one block per CU, so the
+// kernel may use the whole register file instead of spilling)
+template <class Lat, class S, int TX, int TY>
+constexpr int fast_waves_per_eu()
+{
+    return 2 * sizeof(S) * Lat::Q * ((TX + 4) * (TY + 4) + 1) <= 160 * 1024 ? 2 : 1;
+}
+
+template <class Lat, class S, bool DELTA, bool TF, int STAGE, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+    __attribute__((amdgpu_waves_per_eu(fast_waves_per_eu<Lat, S, TX, TY>())))
 sweep_fast(const SweepParams p, const double h, const S *__restrict__ X, const S *__restrict__ F,
            S *__restrict__ out, const S *__restrict__ coef)
 {
     int tx, ty;
     tile_of_block(p, tx, ty);
     if (!tile_is_fast(p, tx * TX, ty * TY, TX, TY)) return;
-    fast_body<Lat, S, DELTA, STAGE, TX, TY>(p, h, X, F, out, coef, tx, ty);
+    fast_body<Lat, S, DELTA, TF, STAGE, TX, TY>(p, h, X, F, out, coef, tx, ty);
 }
 
-template <class Lat, class S, bool DELTA, int STAGE, int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(2)))
+template <class Lat, class S, bool DELTA, bool TF, int STAGE, int TX, int TY>
+__global__ void __launch_bounds__(TX * TY)
+    __attribute__((amdgpu_waves_per_eu(fast_waves_per_eu<Lat, S, TX, TY>())))
 sweep_fast_batched(const SweepParams *__restrict__ P, const StageIO *__restrict__ io,
                    const int4 *__restrict__ work)
 {
     const int4 w = work[blockIdx.x];
     const SweepParams &p = P[w.x];
     const StageIO &a = io[w.x];
-    fast_body<Lat, S, DELTA, STAGE, TX, TY>(p, a.h, (const S *)a.X, (const S *)a.F, (S *)a.out,
-                                           (const S *)a.coef, w.y, w.z);
+    fast_body<Lat, S, DELTA, TF, STAGE, TX, TY>(p, a.h, (const S *)a.X, (const S *)a.F, (S *)a.out,
+                                               (const S *)a.coef, w.y, w.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -398,10 +435,14 @@ sweep_fast_batched(const SweepParams *__restrict__ P, const StageIO *__restrict_
 template <class Lat, class S, bool DELTA, int TX, int TY>
 static hipError_t fast_smem_t(size_t bytes)
 {
-    const void *fns[4] = {(const void *)sweep_fast<Lat, S, DELTA, 0, TX, TY>,
-                          (const void *)sweep_fast<Lat, S, DELTA, 1, TX, TY>,
-                          (const void *)sweep_fast_batched<Lat, S, DELTA, 0, TX, TY>,
-                          (const void *)sweep_fast_batched<Lat, S, DELTA, 1, TX, TY>};
+    const void *fns[8] = {(const void *)sweep_fast<Lat, S, DELTA, false, 0, TX, TY>,
+                          (const void *)sweep_fast<Lat, S, DELTA, false, 1, TX, TY>,
+                          (const void *)sweep_fast<Lat, S, DELTA, true, 0, TX, TY>,
+                          (const void *)sweep_fast<Lat, S, DELTA, true, 1, TX, TY>,
+                          (const void *)sweep_fast_batched<Lat, S, DELTA, false, 0, TX, TY>,
+                          (const void *)sweep_fast_batched<Lat, S, DELTA, false, 1, TX, TY>,
+                          (const void *)sweep_fast_batched<Lat, S, DELTA, true, 0, TX, TY>,
+                          (const void *)sweep_fast_batched<Lat, S, DELTA, true, 1, TX, TY>};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
@@ -415,26 +456,40 @@ static hipError_t fast_launch_t(int stage, const SweepParams &p, double h, const
 {
     const dim3 grid(((p.nx + TX - 1) / TX) * ((p.ny + TY - 1) / TY));
     const size_t smem = sizeof(S) * Lat::Q * ((size_t)(TX + 4) * (TY + 4) + 1);
-    if (stage == 0)
-        hipLaunchKernelGGL((sweep_fast<Lat, S, DELTA, 0, TX, TY>), grid, dim3(TX * TY), smem, s, p, h,
-                           (const S *)X, (const S *)F, (S *)out, (const S *)coef);
-    else
-        hipLaunchKernelGGL((sweep_fast<Lat, S, DELTA, 1, TX, TY>), grid, dim3(TX * TY), smem, s, p, h,
-                           (const S *)X, (const S *)F, (S *)out, (const S *)coef);
+    const dim3 block(TX * TY);
+    const S *x = (const S *)X, *f = (const S *)F, *c = (const S *)coef;
+    S *o = (S *)out;
+    if (p.tau_field) {
+        if (stage == 0)
+            hipLaunchKernelGGL((sweep_fast<Lat, S, DELTA, true, 0, TX, TY>), grid, block, smem, s, p, h, x, f, o, c);
+        else
+            hipLaunchKernelGGL((sweep_fast<Lat, S, DELTA, true, 1, TX, TY>), grid, block, smem, s, p, h, x, f, o, c);
+    } else {
+        if (stage == 0)
+            hipLaunchKernelGGL((sweep_fast<Lat, S, DELTA, false, 0, TX, TY>), grid, block, smem, s, p, h, x, f, o, c);
+        else
+            hipLaunchKernelGGL((sweep_fast<Lat, S, DELTA, false, 1, TX, TY>), grid, block, smem, s, p, h, x, f, o, c);
+    }
     return hipGetLastError();
 }
 
 template <class Lat, class S, bool DELTA, int TX, int TY>
-static hipError_t fast_launch_batched_t(int stage, const SweepParams *P, const StageIO *io, const int4 *work,
-                                        int nwork, size_t smem, hipStream_t s)
+static hipError_t fast_launch_batched_t(int stage, bool tf, const SweepParams *P, const StageIO *io,
+                                        const int4 *work, int nwork, size_t smem, hipStream_t s)
 {
     if (nwork <= 0) return hipSuccess;
-    if (stage == 0)
-        hipLaunchKernelGGL((sweep_fast_batched<Lat, S, DELTA, 0, TX, TY>), dim3(nwork), dim3(TX * TY), smem, s,
-                           P, io, work);
-    else
-        hipLaunchKernelGGL((sweep_fast_batched<Lat, S, DELTA, 1, TX, TY>), dim3(nwork), dim3(TX * TY), smem, s,
-                           P, io, work);
+    const dim3 grid(nwork), block(TX * TY);
+    if (tf) {
+        if (stage == 0)
+            hipLaunchKernelGGL((sweep_fast_batched<Lat, S, DELTA, true, 0, TX, TY>), grid, block, smem, s, P, io, work);
+        else
+            hipLaunchKernelGGL((sweep_fast_batched<Lat, S, DELTA, true, 1, TX, TY>), grid, block, smem, s, P, io, work);
+    } else {
+        if (stage == 0)
+            hipLaunchKernelGGL((sweep_fast_batched<Lat, S, DELTA, false, 0, TX, TY>), grid, block, smem, s, P, io, work);
+        else
+            hipLaunchKernelGGL((sweep_fast_batched<Lat, S, DELTA, false, 1, TX, TY>), grid, block, smem, s, P, io, work);
+    }
     return hipGetLastError();
 }
 
@@ -490,24 +545,26 @@ hipError_t launch_stage_fast(int stage, int lat, bool delta, const SweepParams &
 }
 
 template <class Lat, class S, bool DELTA>
-static hipError_t fast_batched_lat(int stage, int tx, int ty, const SweepParams *P, const StageIO *io,
+static hipError_t fast_batched_lat(int stage, int tx, int ty, bool tf, const SweepParams *P, const StageIO *io,
                                    const int4 *work, int nwork, size_t smem, hipStream_t s)
 {
 #define DUGKS_FS(A, B) \
-    if (tx == A && ty == B) return fast_launch_batched_t<Lat, S, DELTA, A, B>(stage, P, io, work, nwork, smem, s);
+    if (tx == A && ty == B) return fast_launch_batched_t<Lat, S, DELTA, A, B>(stage, tf, P, io, work, nwork, smem, s);
     DUGKS_FAST_SHAPES(DUGKS_FS)
 #undef DUGKS_FS
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_stage_fast_batched(int stage, int lat, bool delta, int tx, int ty, const SweepParams *P,
+hipError_t launch_stage_fast_batched(int stage, int lat, bool delta, int tx, int ty, bool tf, const SweepParams *P,
                                      const StageIO *io, const int4 *work, int nwork, size_t smem,
                                      hipStream_t s)
 {
-    if (lat == 9) return delta ? fast_batched_lat<LatD2Q9, float, true>(stage, tx, ty, P, io, work, nwork, smem, s)
-                               : fast_batched_lat<LatD2Q9, double, false>(stage, tx, ty, P, io, work, nwork, smem, s);
-    if (lat == 37) return delta ? fast_batched_lat<LatD2Q37, float, true>(stage, tx, ty, P, io, work, nwork, smem, s)
-                                : fast_batched_lat<LatD2Q37, double, false>(stage, tx, ty, P, io, work, nwork, smem, s);
+    if (lat == 9)
+        return delta ? fast_batched_lat<LatD2Q9, float, true>(stage, tx, ty, tf, P, io, work, nwork, smem, s)
+                     : fast_batched_lat<LatD2Q9, double, false>(stage, tx, ty, tf, P, io, work, nwork, smem, s);
+    if (lat == 37)
+        return delta ? fast_batched_lat<LatD2Q37, float, true>(stage, tx, ty, tf, P, io, work, nwork, smem, s)
+                     : fast_batched_lat<LatD2Q37, double, false>(stage, tx, ty, tf, P, io, work, nwork, smem, s);
     return hipErrorInvalidValue;
 }
 
