@@ -595,25 +595,29 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
         }
         UP(wm, p.wmom)
     }
+    std::vector<double> lw, md;   // any-size tables, also packed into records below
+    std::vector<int> sg, gnz;
     if (h->lat == 0) {
         // any-size kernels: moment weights and monomials of every velocity
-        std::vector<double> lw(3 * (size_t)nq), md(9 * (size_t)nq);
-        std::vector<float> mf(9 * (size_t)nq);
+        lw.assign(7 * (size_t)nq, 0.0);
+        md.assign(9 * (size_t)nq, 0.0);
         for (int q = 0; q < nq; q++) {
             const double m = h->delta ? d->w[q] : 1.0, x = xi[q], y = eta[q];
-            lw[3 * q] = m;
-            lw[3 * q + 1] = m * x;
-            lw[3 * q + 2] = m * y;
+            lw[7 * q] = m;
+            lw[7 * q + 1] = m * x;
+            lw[7 * q + 2] = m * y;
+            // weights of the flux arriving at a west, east, south, north wall
+            lw[7 * q + 3] = m * std::max(-x, 0.0);
+            lw[7 * q + 4] = m * std::max(x, 0.0);
+            lw[7 * q + 5] = m * std::max(-y, 0.0);
+            lw[7 * q + 6] = m * std::max(y, 0.0);
             const double mono[9] = {x, y, x * x, x * y, y * y, x * x * x, x * x * y, x * y * y, y * y * y};
-            for (int k = 0; k < 9; k++) {
-                md[9 * q + k] = mono[k];
-                mf[9 * q + k] = (float)mono[k];
-            }
+            for (int k = 0; k < 9; k++) md[9 * q + k] = mono[k];
         }
-        std::vector<int> sg(nq);
+        sg.assign(nq, 0);
         for (int q = 0; q < nq; q++)
             sg[q] = (xi[q] > 0 ? 1 : 0) | (xi[q] < 0 ? 2 : 0) | (eta[q] > 0 ? 4 : 0) | (eta[q] < 0 ? 8 : 0);
-        std::vector<int> gnz(nq / p.lq_qs + 1, 0);
+        gnz.assign(nq / p.lq_qs + 1, 0);
         for (int g = 0; g * p.lq_qs + p.lq_qs <= nq; g++) {
             int ok = 1;
             for (int k = 0; k < p.lq_qs; k++) {
@@ -622,7 +626,6 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
             }
             gnz[g] = ok;
         }
-        UP(lw, p.lq_wm) UP(md, p.lq_mono_d) UP(mf, p.lq_mono_f) UP(sg, p.lq_sgn) UP(gnz, p.lq_gnz)
     }
     if (d->tau) {
         std::vector<double> vt(d->tau, d->tau + ncell);
@@ -663,6 +666,34 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
         }
     }
     UP(wallE, p.wall_E)
+    if (h->lat == 0) {
+        // packed per-velocity records in the storage precision
+        auto fill = [&](auto &rec) {
+            using S = decltype(rec[0].wq);
+            for (int q = 0; q < nq; q++) {
+                auto &r = rec[q];
+                r.sg = sg[q];
+                r.gnz = gnz[q / p.lq_qs];
+                for (int k = 0; k < 9; k++) r.mono[k] = (S)md[9 * q + k];
+                r.wq = (S)d->w[q];
+                for (int k = 0; k < 4; k++) r.we[k] = (S)wallE[(size_t)k * nq + q];
+                for (int k = 0; k < 7; k++) r.wm[k] = lw[7 * q + k];
+            }
+        };
+        if (h->delta) {
+            std::vector<QRec<float>> rec(nq);
+            fill(rec);
+            const QRec<float> *dp = nullptr;
+            UP(rec, dp)
+            p.lq_rec = dp;
+        } else {
+            std::vector<QRec<double>> rec(nq);
+            fill(rec);
+            const QRec<double> *dp = nullptr;
+            UP(rec, dp)
+            p.lq_rec = dp;
+        }
+    }
 
     // fast-path coefficients of both stages
     h->h1 = d->dt / 6.0;

@@ -70,14 +70,24 @@ struct SweepParams {
     // large velocity sets: q split into lq_nchunk chunks of lq_chunk velocities,
     // streamed through LDS lq_qs planes at a time
     int lq_chunk, lq_nchunk, lq_qs;
-    const double *lq_wm;     // [nq][3] moment weights (m, m xi, m eta), m = w (FP32-delta) or 1
-    const float *lq_mono_f;  // [nq][9] xi, eta, xi^2, xi eta, eta^2, xi^3, xi^2 eta, xi eta^2, eta^3
-    const double *lq_mono_d;
-    const int *lq_sgn;       // [nq] bit 0: xi > 0, 1: xi < 0, 2: eta > 0, 3: eta < 0
-    const int *lq_gnz;       // [nq / lq_qs + 1] group of lq_qs velocities complete, no zero component
+    const void *lq_rec;      // [nq] QRec<float> (FP32-delta) or QRec<double> (FP64)
 };
 
 // Per-stage arguments of the large-velocity-set kernels.
+// Everything the any-size kernels read per velocity, packed so that a block
+// copies a run of velocities into LDS with plain 32-bit loads.
+template <class S>
+struct QRec {
+    int sg;          // bit 0: xi > 0, 1: xi < 0, 2: eta > 0, 3: eta < 0
+    int gnz;         // the plane group of this velocity is complete with no zero component
+    S mono[9];       // xi, eta, xi^2, xi eta, eta^2, xi^3, xi^2 eta, xi eta^2, eta^3
+    S wq;            // quadrature weight (scales the equilibrium in FP64 storage)
+    S we[4];         // storage-scaled E_q(1, u_w) of the W, E, S, N walls
+    double wm[7];    // m, m xi, m eta, m (-xi)+, m xi+, m (-eta)+, m eta+ (m = w or 1)
+};
+// velocities per LDS copy of the records
+constexpr int LQ_TQ = 64;
+
 struct LQStage {
     const void *X;          // stage input (fhat or tilde f), storage units
     const void *F;          // stage C: fhat(t_n)

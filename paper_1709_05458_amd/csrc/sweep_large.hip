@@ -65,16 +65,31 @@ __device__ __forceinline__ cptr<T> as_const(const T *p)
     return (cptr<T>)p;
 }
 
-template <class S>
-__device__ __forceinline__ cptr<S> mono_table(const SweepParams &p);
-template <>
-__device__ __forceinline__ cptr<float> mono_table<float>(const SweepParams &p) { return as_const(p.lq_mono_f); }
-template <>
-__device__ __forceinline__ cptr<double> mono_table<double>(const SweepParams &p) { return as_const(p.lq_mono_d); }
 
 // Planes of B held in LDS at once (velocities per group).
 template <bool DELTA>
 constexpr int lq_group() { return DELTA ? 4 : 2; }
+
+// LDS row stride of the B planes.  Rows narrower than a half-wave start TX
+// banks apart (stride TX + 32), so the 3 x 3 stencil reads of the rows that
+// share a half-wave hit distinct banks.
+__host__ __device__ inline int lq_row(int tx) { return tx < 32 ? tx + 32 : tx + 2; }
+__host__ __device__ inline int lq_plane(int tx, int ty) { return lq_row(tx) * (ty + 2); }
+
+// Copies the records of velocities qa .. qa+n-1 (clamped to the last one)
+// into LDS with 32-bit loads spread over the block.
+template <class S>
+__device__ __forceinline__ void lq_copy_recs(const SweepParams &p, QRec<S> *dst, int qa, int n)
+{
+    constexpr int NW = (int)(sizeof(QRec<S>) / 4);
+    const unsigned *src = (const unsigned *)p.lq_rec;
+    unsigned *d = (unsigned *)dst;
+    for (int w = threadIdx.x; w < n * NW; w += blockDim.x) {
+        const int r = w / NW, k = w - r * NW;
+        const int q = min(qa + r, p.nq - 1);
+        d[w] = src[(size_t)q * NW + k];
+    }
+}
 
 // ---------------------------------------------------------------------------
 // Ring tiles.  A block of TX x TY threads covers the cells (i0-1 .. i0+TX-2) x
@@ -103,7 +118,7 @@ struct RingCell {
 template <class S>
 __device__ __forceinline__ RingCell<S> ring_cell(const SweepParams &p, int i0, int j0)
 {
-    const int TX = p.tile_x, HX2 = TX + 2;
+    const int TX = p.tile_x, RW = lq_row(TX);
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     RingCell<S> r;
     int gi = i0 - 1 + lx, gj = j0 - 1 + ly;
@@ -115,7 +130,7 @@ __device__ __forceinline__ RingCell<S> ring_cell(const SweepParams &p, int i0, i
     r.active = in;
     r.interior = in && lx >= 1 && lx <= TX - 2 && ly >= 1 && ly <= p.tile_y - 2 && i0 - 1 + lx < p.nx &&
                  j0 - 1 + ly < p.ny;
-    r.slot = (ly + 1) * HX2 + (lx + 1);
+    r.slot = (ly + 1) * RW + (lx + 1);
     r.wW = in && !p.perx && gi == 0;
     r.wE = in && !p.perx && gi == p.nx - 1;
     r.wS = in && !p.pery && gj == 0;
@@ -200,7 +215,7 @@ template <class S>
 __device__ __forceinline__ LQShared<S> lq_shared(const SweepParams &p)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int plane = (p.tile_x + 2) * (p.tile_y + 2);
+    const int plane = lq_plane(p.tile_x, p.tile_y);
     LQShared<S> sh;
     sh.planes = reinterpret_cast<S *>(smem_raw);
     sh.xch = sh.planes + p.lq_qs * plane;
@@ -214,7 +229,8 @@ template <class S>
 struct FillSlots {
     static constexpr int N = 2;
     size_t cell[N];
-    bool use[N];      // slot exists (index < plane)
+    int lds[N];       // index in a plane (padded rows)
+    bool use[N];      // slot exists (index < (TX + 2) (TY + 2))
     S ec[N][6], cc[N];
 };
 
@@ -224,13 +240,14 @@ template <class S, bool DELTA>
 __device__ __forceinline__ FillSlots<S> lq_prepare(const SweepParams &p, const LQStage &a, int i0, int j0)
 {
     const int HX2 = p.tile_x + 2;
-    const int plane = HX2 * (p.tile_y + 2);
+    const int ncl = HX2 * (p.tile_y + 2);
     FillSlots<S> f;
 #pragma unroll
     for (int k = 0; k < FillSlots<S>::N; k++) {
         const int c = threadIdx.x + k * blockDim.x;
-        f.use[k] = c < plane;
+        f.use[k] = c < ncl;
         const int hx = c % HX2, hy = c / HX2;
+        f.lds[k] = hy * lq_row(p.tile_x) + hx;
         int gi = i0 + hx - 2, gj = j0 + hy - 2;
         bool in = f.use[k];
         if (p.perx) gi = wrapi(gi, p.nx); else in = in && gi >= 0 && gi < p.nx;
@@ -277,20 +294,17 @@ __device__ __forceinline__ void lq_load(const SweepParams &p, const LQStage &a, 
 
 // LDS planes q0 .. q0+nqs-1 of B = cc X + ce E (zero outside the domain).
 template <class S, bool DELTA>
-__device__ __forceinline__ void lq_store(const SweepParams &p, LQShared<S> sh, const FillSlots<S> &f, int q0,
-                                         int nqs, const FillLoads<S, DELTA> &v)
+__device__ __forceinline__ void lq_store(const SweepParams &p, LQShared<S> sh, const FillSlots<S> &f,
+                                         const QRec<S> *rq, const FillLoads<S, DELTA> &v)
 {
     constexpr int QS = lq_group<DELTA>();
-    const int plane = (p.tile_x + 2) * (p.tile_y + 2);
-    const cptr<S> MO = mono_table<S>(p);
-    const cptr<double> W = as_const(p.w);
+    const int plane = lq_plane(p.tile_x, p.tile_y);
     S mx[QS], my[QS], mxx[QS], mxy[QS], myy[QS], wq[QS];
 #pragma unroll
     for (int s = 0; s < QS; s++) {
-        const int q = min(q0 + s, p.nq - 1);
-        const cptr<S> m = MO + 9 * q;   // x, y, xx, xy, yy, ...
+        const S *m = rq[s].mono;   // x, y, xx, xy, yy, ...
         mx[s] = m[0]; my[s] = m[1]; mxx[s] = m[2]; mxy[s] = m[3]; myy[s] = m[4];
-        wq[s] = DELTA ? (S)1 : (S)W[q];
+        wq[s] = DELTA ? (S)1 : rq[s].wq;
     }
 #pragma unroll
     for (int k = 0; k < FillSlots<S>::N; k++) {
@@ -304,10 +318,9 @@ __device__ __forceinline__ void lq_store(const SweepParams &p, LQShared<S> sh, c
             e = fmaS(mxy[s], f.ec[k][4], e);
             e = fmaS(myy[s], f.ec[k][5], e);
             // ec and cc are zero outside the domain; planes past nqs are never read
-            sh.planes[s * plane + threadIdx.x + k * blockDim.x] = fmaS(f.cc[k], v.x[k][s], DELTA ? e : wq[s] * e);
+            sh.planes[s * plane + f.lds[k]] = fmaS(f.cc[k], v.x[k][s], DELTA ? e : wq[s] * e);
         }
     }
-    (void)nqs;
 }
 
 // Interface values of one velocity at the faces the thread's cell is upwind
@@ -357,8 +370,8 @@ __device__ __forceinline__ void owned_faces_nz(const RingCell<S> &r, const Deriv
 template <class S, bool DELTA>
 __device__ void lq_faces_body(const SweepParams &p, const LQStage &a, int tile, int chunk)
 {
-    const int TX = p.tile_x, TY = p.tile_y, HX2 = TX + 2;
-    const int plane = HX2 * (TY + 2);
+    const int TX = p.tile_x, TY = p.tile_y, RW = lq_row(TX);
+    const int plane = lq_plane(TX, TY);
     const int NT = TX * TY, t = threadIdx.x;
     LQShared<S> sh = lq_shared<S>(p);
     const int gx = (p.nx + TX - 3) / (TX - 2);
@@ -367,10 +380,7 @@ __device__ void lq_faces_body(const SweepParams &p, const LQStage &a, int tile, 
     const RingCell<S> r = ring_cell<S>(p, i0, j0);
     const S kappa = (S)p.kappa, hs = (S)a.h;
     constexpr int QS = lq_group<DELTA>();
-    const cptr<S> MO = mono_table<S>(p);
-    const cptr<double> WM = as_const(p.lq_wm), XI = as_const(p.xi), ETA = as_const(p.eta);
-    const cptr<int> SG = as_const(p.lq_sgn);
-    const cptr<int> GF = as_const(p.lq_gnz);
+    __shared__ QRec<S> recs[LQ_TQ];   // per-velocity data of the current run of velocities
     // domain-boundary faces of the cell
     const bool wallW = r.wW, wallE = r.wE, wallS = r.wS, wallN = r.wN;
     S *xw = sh.xch, *xe = sh.xch + QS * NT, *ys = sh.xch + 2 * QS * NT, *yn = sh.xch + 3 * QS * NT;
@@ -387,56 +397,68 @@ __device__ void lq_faces_body(const SweepParams &p, const LQStage &a, int tile, 
     }
 
     const FillSlots<S> fsl = lq_prepare<S, DELTA>(p, a, i0, j0);
-    double acc[4][4];   // faces W, E, S, N x (sum m x, sum m xi x, sum m eta x, diffuse numerator)
+    double acc[4][3];   // faces W, E, S, N x (sum m x, sum m xi x, sum m eta x)
 #pragma unroll
     for (int f = 0; f < 4; f++)
 #pragma unroll
-        for (int k = 0; k < 4; k++) acc[f][k] = 0.0;
+        for (int k = 0; k < 3; k++) acc[f][k] = 0.0;
+    // diffuse-wall numerators of the faces W, E, S, N (separate scalars: the
+    // compiler must not turn the sign choice below into an indexed store)
+    double dnW = 0.0, dnE = 0.0, dnS = 0.0, dnN = 0.0;
     FillLoads<S, DELTA> ld;
     lq_load<S, DELTA>(p, a, fsl, q0, min(QS, q1 - q0), ld);
 
-    // interior threads: store the face values of one velocity and add their moments
-    auto finish = [&](int q, S fw, S fe, S fs, S fn, double w0, double w1, double w2, double xq, double yq) {
+    // interior threads: store the face values of one velocity and add their
+    // moments.  WALL: the tile has domain-boundary cells (the east / north
+    // faces of wall cells and the diffuse-wall sums are then added too).
+    auto finish = [&](auto wall, int q, S fw, S fe, S fs, S fn, const double *m) {
+        const double w0 = m[0], w1 = m[1], w2 = m[2];
+        constexpr bool WALL = decltype(wall)::value;
         FX[(size_t)q * nxf + fid[0]] = fw;
         FY[(size_t)q * nyf + fid[2]] = fs;
-        if (wallE) FX[(size_t)q * nxf + fid[1]] = fe;
-        if (wallN) FY[(size_t)q * nyf + fid[3]] = fn;
+        if (WALL && wallE) FX[(size_t)q * nxf + fid[1]] = fe;
+        if (WALL && wallN) FY[(size_t)q * nyf + fid[3]] = fn;
         const double v[4] = {(double)fw, (double)fe, (double)fs, (double)fn};
+        // with WALL every lane also sums its east / north faces and the wall
+        // numerators (no per-lane selects); only wall faces use those sums
 #pragma unroll
         for (int f = 0; f < 4; f++) {
-            if ((f == 1 && !wallE) || (f == 3 && !wallN)) continue;
+            if (!WALL && (f == 1 || f == 3)) continue;
             acc[f][0] = __builtin_fma(w0, v[f], acc[f][0]);
             acc[f][1] = __builtin_fma(w1, v[f], acc[f][1]);
             acc[f][2] = __builtin_fma(w2, v[f], acc[f][2]);
         }
-        // arriving at a wall: sum of |xi.n| m fbar (eq. of the diffuse-scattering rule)
-        if (wallW && xq < 0.0) acc[0][3] = __builtin_fma(-xq * w0, v[0], acc[0][3]);
-        if (wallE && xq > 0.0) acc[1][3] = __builtin_fma(xq * w0, v[1], acc[1][3]);
-        if (wallS && yq < 0.0) acc[2][3] = __builtin_fma(-yq * w0, v[2], acc[2][3]);
-        if (wallN && yq > 0.0) acc[3][3] = __builtin_fma(yq * w0, v[3], acc[3][3]);
+        if (!WALL) return;
+        // arriving at a wall: sum of (xi.n)+ m fbar (eq. of the diffuse-scattering rule)
+        dnW = __builtin_fma(m[3], v[0], dnW);
+        dnE = __builtin_fma(m[4], v[1], dnE);
+        dnS = __builtin_fma(m[5], v[2], dnS);
+        dnN = __builtin_fma(m[6], v[3], dnN);
     };
 
     // one group of QS velocities; NZ: all present and no zero component (one
-    // upwind face per axis); FULL: all present
-    auto group = [&](auto nz, auto full, int qa, int nqs) {
+    // upwind face per axis); FULL: all present; WALL as for finish
+    auto group = [&](auto nz, auto full, auto wall, int qa, int nqs, const QRec<S> *rq) {
         constexpr bool NZ = decltype(nz)::value, FULL = decltype(full)::value;
+        constexpr bool WALL = decltype(wall)::value;
         int sgv[QS];
         S xh[QS], yh[QS];
 #pragma unroll
         for (int s = 0; s < QS; s++) {
-            const int q = min(qa + s, p.nq - 1);
-            sgv[s] = SG[q];
-            xh[s] = MO[9 * q] * hs;
-            yh[s] = MO[9 * q + 1] * hs;
+            sgv[s] = rq[s].sg;
+            xh[s] = rq[s].mono[0] * hs;
+            yh[s] = rq[s].mono[1] * hs;
         }
-        __syncthreads();
-        lq_store<S, DELTA>(p, sh, fsl, qa, nqs, ld);
+        // no barrier needed before the store: every thread has passed the
+        // previous group's last barrier, so the planes are no longer read, and
+        // the exchange buffer is rewritten only after the next barrier
+        lq_store<S, DELTA>(p, sh, fsl, rq, ld);
         __syncthreads();
         if (qa + QS < q1) lq_load<S, DELTA>(p, a, fsl, qa + QS, min(QS, q1 - qa - QS), ld);
 #pragma unroll
         for (int s = 0; s < QS; s++) {
             if (!FULL && s >= nqs) break;
-            const Deriv<S> d = derivs<S>(r, sh.planes + s * plane, HX2);
+            const Deriv<S> d = derivs<S>(r, sh.planes + s * plane, RW);
             if (NZ) {
                 S vx, vy;
                 owned_faces_nz<S>(r, d, sgv[s] & 1, sgv[s] & 4, xh[s], yh[s], kappa, vx, vy);
@@ -450,6 +472,8 @@ __device__ void lq_faces_body(const SweepParams &p, const LQStage &a, int tile, 
                 ys[s * NT + t] = fv[2];
                 yn[s * NT + t] = fv[3];
             }
+            // one velocity at a time (register pressure)
+            __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();
         if (!r.interior) return;
@@ -457,33 +481,52 @@ __device__ void lq_faces_body(const SweepParams &p, const LQStage &a, int tile, 
         for (int s = 0; s < QS; s++) {
             if (!FULL && s >= nqs) break;
             const int q = qa + s, sg = sgv[s], b = s * NT + t;
-            const cptr<double> m = WM + 3 * q;
+            const double *m = rq[s].wm;
             S fw, fe, fs, fn;
             if (NZ) {
                 const int bx = (sg & 1) ? b - 1 : b, by = (sg & 4) ? b - TX : b;
-                fw = xw[bx]; fe = xw[bx + 1]; fs = ys[by]; fn = ys[by + TX];
+                fw = xw[bx]; fs = ys[by];
+                fe = WALL ? xw[bx + 1] : (S)0;
+                fn = WALL ? ys[by + TX] : (S)0;
             } else {
                 fw = xe[b - 1] + xw[b]; fe = xe[b] + xw[b + 1];
                 fs = yn[b - TX] + ys[b]; fn = yn[b] + ys[b + TX];
             }
-            finish(q, fw, fe, fs, fn, m[0], m[1], m[2], XI[q], ETA[q]);
+            finish(wall, q, fw, fe, fs, fn, m);
             // one velocity at a time (register pressure)
             __builtin_amdgcn_sched_barrier(0);
         }
     };
+    // tiles whose interior holds no cell next to a non-periodic wall
+    const bool twall = (!p.perx && (i0 == 0 || i0 + TX - 2 >= p.nx)) ||
+                       (!p.pery && (j0 == 0 || j0 + TY - 2 >= p.ny));
     for (int qa = q0; qa < q1; qa += QS) {
-        if (GF[qa / QS]) group(std::true_type{}, std::true_type{}, qa, QS);
-        else group(std::false_type{}, std::false_type{}, qa, min(QS, q1 - qa));
+        const int ql = (qa - q0) % LQ_TQ;
+        if (ql == 0) {
+            // every thread is past its last use of the previous run's records
+            __syncthreads();
+            lq_copy_recs<S>(p, recs, qa, min(LQ_TQ, (q1 - qa + QS - 1) / QS * QS));
+            __syncthreads();
+        }
+        const QRec<S> *rq = recs + ql;
+        if (__builtin_amdgcn_readfirstlane(rq[0].gnz)) {
+            if (twall) group(std::true_type{}, std::true_type{}, std::true_type{}, qa, QS, rq);
+            else group(std::true_type{}, std::true_type{}, std::false_type{}, qa, QS, rq);
+        } else {
+            group(std::false_type{}, std::false_type{}, std::true_type{}, qa, min(QS, q1 - qa), rq);
+        }
     }
     if (!r.interior) return;
     const long long nface = (long long)nxf + (long long)nyf;
     double *part = a.face_part + (long long)chunk * nface * 4;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        part[4 * fid[0] + k] = acc[0][k];
-        part[4 * (nxf + fid[2]) + k] = acc[2][k];
-        if (wallE) part[4 * fid[1] + k] = acc[1][k];
-        if (wallN) part[4 * (nxf + fid[3]) + k] = acc[3][k];
+        const double a0 = k < 3 ? acc[0][k] : dnW, a1 = k < 3 ? acc[1][k] : dnE;
+        const double a2 = k < 3 ? acc[2][k] : dnS, a3 = k < 3 ? acc[3][k] : dnN;
+        part[4 * fid[0] + k] = a0;
+        part[4 * (nxf + fid[2]) + k] = a2;
+        if (wallE) part[4 * fid[1] + k] = a1;
+        if (wallN) part[4 * (nxf + fid[3]) + k] = a3;
     }
 }
 
@@ -549,10 +592,14 @@ __device__ void lq_face_reduce_body(const SweepParams &p, const LQStage &a, bool
 template <class S, bool DELTA>
 __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int block, int chunk)
 {
-    const long long cell = (long long)block * blockDim.x + threadIdx.x;
-    if (cell >= p.ncell) return;
+    // threads past the last cell work on the last cell and store nothing
+    // (every thread takes part in the record copies and their barriers)
+    const long long cell0 = (long long)block * blockDim.x + threadIdx.x;
+    const bool valid = cell0 < p.ncell;
+    const long long cell = valid ? cell0 : p.ncell - 1;
     const int i = (int)(cell % p.nx), j = (int)(cell / p.nx);
     const int q0 = chunk * p.lq_chunk, q1 = min(p.nq, q0 + p.lq_chunk);
+    __shared__ QRec<S> recs[LQ_TQ];
     const double dt = p.dt, h = a.h;
     const size_t nxf = (size_t)(p.nx + 1) * p.ny, nyf = (size_t)p.nx * (p.ny + 1);
     const long long fidl[4] = {xface_id(p, i, j), xface_id(p, i + 1, j), yface_id(p, i, j), yface_id(p, i, j + 1)};
@@ -661,13 +708,16 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int block
     const S *__restrict__ FX = (const S *)a.fxv;
     const S *__restrict__ FY = (const S *)a.fyv;
     S *__restrict__ out = (S *)a.out;
-    const cptr<S> MO = mono_table<S>(p);
-    const cptr<double> WM = as_const(p.lq_wm), W = as_const(p.w), WE = as_const(p.wall_E);
-    const cptr<int> SG = as_const(p.lq_sgn);
     const size_t n = (size_t)p.ncell;
     double m0 = 0, m1 = 0, m2 = 0;   // partial cell moments of the output
     constexpr int U = 4;             // velocities whose loads are issued together
     for (int qa = q0; qa < q1; qa += U) {
+        const int ql = (qa - q0) % LQ_TQ;
+        if (ql == 0) {
+            __syncthreads();
+            lq_copy_recs<S>(p, recs, qa, min(LQ_TQ, (q1 - qa + U - 1) / U * U));
+            __syncthreads();
+        }
         S fw[U], fe[U], fs[U], fn[U], xo[U], fo[U];
 #pragma unroll
         for (int u = 0; u < U; u++) {
@@ -683,31 +733,33 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int block
         for (int u = 0; u < U; u++) {
             const int q = qa + u;
             if (q >= q1) break;
-            const int sg = SG[q];
-            const cptr<S> mo = MO + 9 * q;
+            const QRec<S> &rq = recs[ql + u];
+            const int sg = rq.sg;
+            const S *mo = rq.mono;
             S w_ = fw[u], e_ = fe[u], s_ = fs[u], n_ = fn[u];
             // velocities leaving a diffuse wall: fbar = E(rho_w, u_w)
-            if (dsf[0] && (sg & 1)) w_ = rws[0] * (S)WE[q] - r0s;
-            if (dsf[1] && (sg & 2)) e_ = rws[1] * (S)WE[p.nq + q] - r0s;
-            if (dsf[2] && (sg & 4)) s_ = rws[2] * (S)WE[2 * p.nq + q] - r0s;
-            if (dsf[3] && (sg & 8)) n_ = rws[3] * (S)WE[3 * p.nq + q] - r0s;
+            if (dsf[0] && (sg & 1)) w_ = rws[0] * rq.we[0] - r0s;
+            if (dsf[1] && (sg & 2)) e_ = rws[1] * rq.we[1] - r0s;
+            if (dsf[2] && (sg & 4)) s_ = rws[2] * rq.we[2] - r0s;
+            if (dsf[3] && (sg & 8)) n_ = rws[3] * rq.we[3] - r0s;
             const S La = fmaS(mo[0] * cx, fmaS(alpha[1], e_, -alpha[0] * w_),
                               mo[1] * cy * fmaS(alpha[3], n_, -alpha[2] * s_));
             S Mq = M[0];
 #pragma unroll
             for (int k = 0; k < 9; k++) Mq = fmaS(mo[k], M[k + 1], Mq);
-            const S sq = DELTA ? (S)1 : (S)W[q];
+            const S sq = DELTA ? (S)1 : rq.wq;
             S R = kx_own * xo[u];
             if (a.stage != 0) R = fmaS(kf_own, fo[u], R);
             const S y = fmaS(aL, La, fmaS(sq, Mq, R));
-            out[(size_t)q * n + cell] = y;
-            const cptr<double> w3 = WM + 3 * q;
+            if (valid) out[(size_t)q * n + cell] = y;
+            const double *w3 = rq.wm;
             const double yd = (double)y;
             m0 = __builtin_fma(w3[0], yd, m0);
             m1 = __builtin_fma(w3[1], yd, m1);
             m2 = __builtin_fma(w3[2], yd, m2);
         }
     }
+    if (!valid) return;
     double *cp = a.cell_part + ((long long)chunk * p.ncell + cell) * 4;
     cp[0] = m0; cp[1] = m1; cp[2] = m2; cp[3] = 0.0;
 }
@@ -770,7 +822,8 @@ __global__ void k_state_moments(const SweepParams p, const S *__restrict__ x, do
 // (params table + work list of (instance, tile, chunk)).
 // ---------------------------------------------------------------------------
 template <class S, bool DELTA>
-__global__ void __launch_bounds__(256) lq_faces(const SweepParams p, const LQStage a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+lq_faces(const SweepParams p, const LQStage a)
 {
     const int ntile = lq_ntile(p);
     lq_faces_body<S, DELTA>(p, a, blockIdx.x % ntile, blockIdx.x / ntile);
@@ -796,7 +849,8 @@ __global__ void __launch_bounds__(256) lq_cell_reduce(const SweepParams p, const
 }
 
 template <class S, bool DELTA>
-__global__ void __launch_bounds__(256) lq_faces_batched(const SweepParams *__restrict__ P,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+lq_faces_batched(const SweepParams *__restrict__ P,
                                                         const LQStage *__restrict__ A,
                                                         const int4 *__restrict__ work)
 {
@@ -856,13 +910,11 @@ hipError_t launch_lq_stage_batched(bool delta, const SweepParams *P, const LQSta
 
 size_t lq_smem_bytes(const SweepParams &p, bool delta)
 {
-    // planes and equilibrium coefficients over the tile and halo, interface
-    // exchange; the interface-moment exchange of lq_faces (16 doubles per
-    // thread) reuses the same space
-    const size_t plane = (size_t)(p.tile_x + 2) * (p.tile_y + 2);
+    // B planes over the tile and halo (padded rows) and the interface
+    // exchange (the per-velocity records are static LDS of the kernels)
+    const size_t plane = (size_t)lq_plane(p.tile_x, p.tile_y);
     const size_t nt = (size_t)p.tile_x * p.tile_y;
-    const size_t a = (delta ? 4 : 8) * (plane * p.lq_qs + 4 * (size_t)p.lq_qs * nt);
-    return std::max(a, 16 * 8 * nt);
+    return (delta ? 4 : 8) * (plane * p.lq_qs + 4 * (size_t)p.lq_qs * nt);
 }
 
 template <class S, bool DELTA>
