@@ -514,13 +514,38 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
             delete h;
             return fail(DUGKS_EINVAL, "any-size velocity sets need tiles of at least 4 x 4 threads");
         }
-        const long long ntile = lq_ntile(p);
-        int nch = (int)std::max(1LL, (2048 + ntile - 1) / ntile);
-        nch = std::min(nch, std::max(1, nq / 16));
         p.lq_qs = h->delta ? 4 : 2;
-        p.lq_chunk = (nq + nch - 1) / nch;
-        p.lq_chunk = (p.lq_chunk + p.lq_qs - 1) / p.lq_qs * p.lq_qs;   // whole plane groups
+        // Velocity chunks: at least two rounds of the blocks the chip holds at
+        // once, and a chunk count whose last round is as full as possible
+        // (every block of a kernel costs about the same).
+        int dev = 0, ncu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+            ncu = 256;
+        const long long slots_f =
+            (long long)ncu * lq_blocks_per_cu(h->delta, true, lx * ly, lq_smem_bytes(p, h->delta));
+        const long long slots_u = (long long)ncu * lq_blocks_per_cu(h->delta, false, 256, 0);
+        // per: blocks per chunk; chunk lengths are multiples of step and at least minq
+        auto pick = [&](long long per, long long slots, int step, int minq) {
+            const long long nmax = std::max(1, nq / minq);
+            const long long nlo = std::min(nmax, std::max(1LL, (2 * slots + per - 1) / per));
+            const long long nhi = std::min(nmax, 3 * nlo);
+            int best = 0;
+            double best_eff = -1.0;
+            for (long long nch = nlo; nch <= nhi; nch++) {
+                int c = (int)((nq + nch - 1) / nch);
+                c = (c + step - 1) / step * step;
+                const long long blocks = per * ((nq + c - 1) / c);
+                const long long rounds = (blocks + slots - 1) / slots;
+                const double eff = (double)blocks / (double)(rounds * slots);
+                if (eff > best_eff + 1e-9) { best_eff = eff; best = c; }
+            }
+            return best;
+        };
+        p.lq_chunk = pick(lq_ntile(p), slots_f, p.lq_qs, 16);
         p.lq_nchunk = (nq + p.lq_chunk - 1) / p.lq_chunk;
+        p.lq_uchunk = pick((ncell + 255) / 256, slots_u, 4, 32);
+        p.lq_nuchunk = (nq + p.lq_uchunk - 1) / p.lq_uchunk;
     }
     // lattice kernels: one plane of the tile and its halo per velocity, plus one
     // spare element per plane (compile-time-shape kernels)
@@ -729,7 +754,7 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
         void *a = nullptr, *b = nullptr, *fp = nullptr, *fm = nullptr, *cp = nullptr;
         if ((rc = dalloc(h, &a, 32 * (size_t)ncell)) || (rc = dalloc(h, &b, 32 * (size_t)ncell)) ||
             (rc = dalloc(h, &fp, 32 * nface * p.lq_nchunk)) || (rc = dalloc(h, &fm, 64 * nface)) ||
-            (rc = dalloc(h, &cp, 32 * (size_t)ncell * p.lq_nchunk))) {
+            (rc = dalloc(h, &cp, 32 * (size_t)ncell * p.lq_nuchunk))) {
             dugks_destroy(h);
             return rc;
         }
@@ -756,8 +781,9 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
         snprintf(buf, sizeof buf, "lattice D2Q%d %s tile %dx%d %s", h->lat, h->delta ? "fp32-delta" : "fp64",
                  lx, ly, unif ? "uniform" : "non-uniform");
     else
-        snprintf(buf, sizeof buf, "any-size Q=%d %s tile %dx%d, %d chunks of %d velocities, %s", nq,
-                 h->delta ? "fp32-delta" : "fp64", lx, ly, p.lq_nchunk, p.lq_chunk,
+        snprintf(buf, sizeof buf,
+                 "any-size Q=%d %s tile %dx%d, %d chunks of %d velocities (update: %d of %d), %s", nq,
+                 h->delta ? "fp32-delta" : "fp64", lx, ly, p.lq_nchunk, p.lq_chunk, p.lq_nuchunk, p.lq_uchunk,
                  unif ? "uniform" : "non-uniform");
     h->variant = buf;
     *out = h;
@@ -1131,7 +1157,7 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
             const long long nface = (long long)(p.nx + 1) * p.ny + (long long)p.nx * (p.ny + 1);
             for (long long f = 0; f < (nface + 255) / 256; f++) faces.push_back(make_int4(k, (int)f, 0, 0));
             for (long long f = 0; f < (p.ncell + 255) / 256; f++) cells.push_back(make_int4(k, (int)f, 0, 0));
-            for (int ch = 0; ch < p.lq_nchunk; ch++)
+            for (int ch = 0; ch < p.lq_nuchunk; ch++)
                 for (long long f = 0; f < (p.ncell + 255) / 256; f++) upd.push_back(make_int4(k, (int)f, ch, 0));
         }
         b->nlq_tiles = (int)tiles.size();

@@ -70,6 +70,8 @@ struct SweepParams {
     // large velocity sets: q split into lq_nchunk chunks of lq_chunk velocities,
     // streamed through LDS lq_qs planes at a time
     int lq_chunk, lq_nchunk, lq_qs;
+    // lq_update's own split of q (its work items are 256 cells x lq_uchunk velocities)
+    int lq_uchunk, lq_nuchunk;
     const void *lq_rec;      // [nq] QRec<float> (FP32-delta) or QRec<double> (FP64)
 };
 
@@ -155,6 +157,8 @@ __host__ __device__ inline int lq_ntile(const SweepParams &p)
 }
 hipError_t set_lq_smem(bool delta, size_t bytes);
 size_t lq_smem_bytes(const SweepParams &p, bool delta);
+// resident blocks of lq_faces (faces = true) or lq_update on one CU
+int lq_blocks_per_cu(bool delta, bool faces, int nthreads, size_t smem);
 hipError_t launch_state_moments(const SweepParams &p, bool delta, const void *state, double *mom,
                                 hipStream_t s);
 

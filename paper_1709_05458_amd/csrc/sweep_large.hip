@@ -598,7 +598,7 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int block
     const bool valid = cell0 < p.ncell;
     const long long cell = valid ? cell0 : p.ncell - 1;
     const int i = (int)(cell % p.nx), j = (int)(cell / p.nx);
-    const int q0 = chunk * p.lq_chunk, q1 = min(p.nq, q0 + p.lq_chunk);
+    const int q0 = chunk * p.lq_uchunk, q1 = min(p.nq, q0 + p.lq_uchunk);
     __shared__ QRec<S> recs[LQ_TQ];
     const double dt = p.dt, h = a.h;
     const size_t nxf = (size_t)(p.nx + 1) * p.ny, nyf = (size_t)p.nx * (p.ny + 1);
@@ -771,7 +771,7 @@ __device__ void lq_cell_reduce_body(const SweepParams &p, const LQStage &a, bool
 {
     if (cell >= p.ncell) return;
     double s0 = 0, sx = 0, sy = 0;
-    for (int c = 0; c < p.lq_nchunk; c++) {
+    for (int c = 0; c < p.lq_nuchunk; c++) {
         const double *v = a.cell_part + ((long long)c * p.ncell + cell) * 4;
         s0 += v[0];
         sx += v[1];
@@ -929,7 +929,7 @@ static hipError_t lq_stage_t(const SweepParams &p, const LQStage &a, hipStream_t
     if (part == 1 || part < 0)
         hipLaunchKernelGGL((lq_face_reduce<DELTA>), dim3((unsigned)((nface + 255) / 256)), dim3(256), 0, s, p, a);
     if (part == 2 || part < 0)
-        hipLaunchKernelGGL((lq_update<S, DELTA>), dim3((unsigned)((p.ncell + 255) / 256) * p.lq_nchunk), dim3(256),
+        hipLaunchKernelGGL((lq_update<S, DELTA>), dim3((unsigned)((p.ncell + 255) / 256) * p.lq_nuchunk), dim3(256),
                            0, s, p, a);
     if (part == 3 || part < 0)
         hipLaunchKernelGGL((lq_cell_reduce<DELTA>), dim3((unsigned)((p.ncell + 255) / 256)), dim3(256), 0, s, p, a);
@@ -939,6 +939,18 @@ static hipError_t lq_stage_t(const SweepParams &p, const LQStage &a, hipStream_t
 hipError_t launch_lq_stage(bool delta, const SweepParams &p, const LQStage &a, hipStream_t s, int part)
 {
     return delta ? lq_stage_t<float, true>(p, a, s, part) : lq_stage_t<double, false>(p, a, s, part);
+}
+
+int lq_blocks_per_cu(bool delta, bool faces, int nthreads, size_t smem)
+{
+    const void *f = delta ? (faces ? (const void *)lq_faces<float, true> : (const void *)lq_update<float, true>)
+                          : (faces ? (const void *)lq_faces<double, false> : (const void *)lq_update<double, false>);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, nthreads, smem) != hipSuccess || nb < 1) {
+        (void)hipGetLastError();
+        nb = 1;
+    }
+    return nb;
 }
 
 hipError_t set_lq_smem(bool delta, size_t bytes)
