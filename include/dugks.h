@@ -64,6 +64,17 @@ enum dugks_precision {
 
 enum dugks_mem { DUGKS_MEM_HOST = 0, DUGKS_MEM_DEVICE = 1 };
 
+/* Time integrator.  T3S3: the paper's third-order two-stage step (steps
+ * (1)-(4), eq. feqIntD3rdHat2_DS), state fhat = f - (dt/4) Omega.  T2S3: the
+ * second-order step the paper compares against (Remark I, eq.
+ * feqIntD2nd_Explicit with the full step on the flux) with the same
+ * third-order interface reconstruction (eq. flux_DS): state
+ * ftilde = f - (dt/2) Omega, one reconstruction per step over h = dt/2,
+ *     ftilde(t+dt) = ((2 tau - dt) ftilde + 2 dt E) / (2 tau + dt) + dt L,
+ * where L is the micro-flux of fbar^{+,h} = ((4 tau - dt) ftilde + 3 dt E) / (4 tau + 2 dt)
+ * reconstructed at the faces and recovered (eq. recover2f). */
+enum dugks_scheme { DUGKS_SCHEME_T3S3 = 0, DUGKS_SCHEME_T2S3 = 1 };
+
 enum dugks_flags {
     DUGKS_ALLOW_MOMENT_DEFECT = 1,  /* accept weights that are not moment-exact (e.g. Newton-Cotes) */
     DUGKS_FORCE_GENERIC = 2         /* use the any-size velocity-set kernels even for D2Q9 / D2Q37 */
@@ -95,6 +106,9 @@ typedef struct {
     void *stream;           /* hipStream_t for all work, NULL = null stream */
     int flags;              /* dugks_flags */
     int tile_x, tile_y;     /* sweep tile in cells; 0 = library choice */
+    int scheme;             /* dugks_scheme; 0 = T3S3.  T2S3 has no dt/tau bound
+                             * (its relaxation factor stays in (-1, 1)); dugks_backward
+                             * and batches take T3S3 only (DUGKS_ENOTSUP / DUGKS_EINVAL) */
 } dugks_desc;
 
 /* Build a solver for one grid / velocity set / relaxation field (paper:
@@ -116,24 +130,26 @@ int dugks_create(const dugks_desc *d, dugks_t **out);
 int dugks_destroy(dugks_t *h);
 
 /* State at t_n from the physical distribution f [q][cell]; the library stores
- * fhat = f - (dt/4) Omega(f) (paper eq. feqIntD3rdHat2 definitions). */
+ * fhat = f - (dt/4) Omega(f) (paper eq. feqIntD3rdHat2 definitions), or for
+ * DUGKS_SCHEME_T2S3 ftilde = f - (dt/2) Omega(f). */
 int dugks_set_state(dugks_t *h, const double *f, int mem);
 
 /* f = E(rho, u) at every cell (paper: initial state is the equilibrium). */
 int dugks_init_equilibrium(dugks_t *h, const double *rho, const double *ux,
                            const double *uy, int mem);
 
-/* Advance nsteps T3S3 steps (asynchronous on the stream). */
+/* Advance nsteps steps of the handle's scheme (asynchronous on the stream). */
 int dugks_step(dugks_t *h, int nsteps);
 
 /* Cell density and velocity [cell] of the current state (moments of fhat,
  * which equal those of f for moment-exact weights). */
 int dugks_moments(dugks_t *h, double *rho, double *ux, double *uy, int mem);
 
-/* Physical distribution f = (4 tau fhat + dt E) / (4 tau + dt), [q][cell]. */
+/* Physical distribution f = (4 tau fhat + dt E) / (4 tau + dt), [q][cell]
+ * (T2S3: f = (2 tau ftilde + dt E) / (2 tau + dt)). */
 int dugks_get_state(dugks_t *h, double *f, int mem);
 
-/* The stored variable fhat itself, [q][cell], in double. */
+/* The stored variable (fhat, or ftilde for T2S3) itself, [q][cell], in double. */
 int dugks_get_fhat(dugks_t *h, double *fhat, int mem);
 
 /* Replace the relaxation-time field ([cell], > 0, dt/tau <= 12). */
@@ -160,8 +176,8 @@ int dugks_sync(dugks_t *h);
  * returns.  The adjoint arithmetic is double for both precisions (for
  * DUGKS_FP32_DELTA it linearises around the FP32 trajectory).  No atomics:
  * results are bitwise reproducible.  The handle's state is left unchanged.
- * Periodic uniform grids only (else DUGKS_ENOTSUP); batch handles:
- * DUGKS_ENOTSUP; nsteps < 0 or ckpt_every < 1: DUGKS_EINVAL. */
+ * Periodic uniform grids and the T3S3 scheme only (else DUGKS_ENOTSUP); batch
+ * handles: DUGKS_ENOTSUP; nsteps < 0 or ckpt_every < 1: DUGKS_EINVAL. */
 int dugks_backward(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
                    const double *dL_drho, const double *dL_du,
                    double *dL_df0, double *dL_dtau, int mem);

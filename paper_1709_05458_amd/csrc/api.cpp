@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/dugks.h"
@@ -348,6 +349,8 @@ static int validate(const dugks_desc *d)
     if (d->nx < 3 || d->ny < 3) return fail(DUGKS_EINVAL, "nx and ny must be >= 3");
     if (!d->xf || !d->yf || !d->xi || !d->w) return fail(DUGKS_EINVAL, "null grid or velocity array");
     if (d->nq < 1) return fail(DUGKS_EINVAL, "nq must be >= 1");
+    if (d->scheme != DUGKS_SCHEME_T3S3 && d->scheme != DUGKS_SCHEME_T2S3)
+        return fail(DUGKS_EINVAL, "unknown scheme");
     for (int i = 0; i < d->nx; i++)
         if (!(d->xf[i + 1] > d->xf[i])) return fail(DUGKS_EINVAL, "xf not increasing");
     for (int j = 0; j < d->ny; j++)
@@ -370,16 +373,20 @@ static int validate(const dugks_desc *d)
     return DUGKS_OK;
 }
 
-static int check_tau(const double *tau, long long n, double tau0, double dt)
+// T3S3 is stable for dt/tau <= 12 (the von Neumann bound of the paper's
+// homogeneous factor at a = 1/3); the T2 step's factor (2 tau - dt)/(2 tau + dt)
+// stays in (-1, 1) for every dt/tau, so T2S3 has no such bound.
+static int check_tau(const double *tau, long long n, double tau0, double dt, bool t2)
 {
+    const double bound = t2 ? HUGE_VAL : 12.0 * (1 + 1e-12);
     if (tau) {
         for (long long k = 0; k < n; k++) {
             if (!(tau[k] > 0)) return fail(DUGKS_EINVAL, "tau must be > 0");
-            if (dt / tau[k] > 12.0 * (1 + 1e-12)) return fail(DUGKS_EUNSTABLE, "dt/tau > 12");
+            if (dt / tau[k] > bound) return fail(DUGKS_EUNSTABLE, "dt/tau > 12");
         }
     } else {
         if (!(tau0 > 0)) return fail(DUGKS_EINVAL, "tau0 must be > 0");
-        if (dt / tau0 > 12.0 * (1 + 1e-12)) return fail(DUGKS_EUNSTABLE, "dt/tau > 12");
+        if (dt / tau0 > bound) return fail(DUGKS_EUNSTABLE, "dt/tau > 12");
     }
     return DUGKS_OK;
 }
@@ -391,7 +398,7 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     int rc = validate(d);
     if (rc) return rc;
     const long long ncell = (long long)d->nx * d->ny;
-    if ((rc = check_tau(d->tau, ncell, d->tau0, d->dt))) return rc;
+    if ((rc = check_tau(d->tau, ncell, d->tau0, d->dt, d->scheme == DUGKS_SCHEME_T2S3))) return rc;
     const int nq = d->nq;
     const double *xi = d->xi, *eta = d->xi + nq;
 
@@ -435,6 +442,7 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     p.nx = d->nx;
     p.ny = d->ny;
     p.ncell = ncell;
+    p.t2 = d->scheme == DUGKS_SCHEME_T2S3;
     p.perx = d->bc[0] == DUGKS_BC_PERIODIC;
     p.pery = d->bc[2] == DUGKS_BC_PERIODIC;
     p.nq = nq;
@@ -475,11 +483,16 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     if (const char *e = getenv("DUGKS_NXCD")) p.nxcd = std::max(1, atoi(e));   // tuning knob
     p.iRT = 1.0 / d->RT;
     {
-        // coefficients of a uniform tau (used when no tau field is given)
-        const double t = d->tau0, dt = d->dt, h1 = dt / 6.0, h2 = 5.0 * dt / 12.0;
+        // coefficients of a uniform tau (used when no tau field is given);
+        // stage A of T3S3 reconstructs over dt/6, the T2S3 step over dt/2
+        const double t = d->tau0, dt = d->dt, h1 = p.t2 ? 0.5 * dt : dt / 6.0, h2 = 5.0 * dt / 12.0;
         UniformCoef &u = p.uc;
-        u.cc[0] = (12.0 * t - dt) / (12.0 * t + 3.0 * dt);
-        u.ce[0] = 4.0 * dt / (12.0 * t + 3.0 * dt);
+        const Stage0Coef c0 = stage0_coef(p.t2 != 0, t, dt);
+        u.cc[0] = c0.cc;
+        u.ce[0] = c0.ce;
+        u.kx0 = c0.kx;
+        u.ke0 = c0.ke;
+        u.aL0 = p.t2 ? dt : dt / 3.0;
         u.cc[1] = (24.0 * t - 5.0 * dt) / (24.0 * t + 4.0 * dt);
         u.ce[1] = 9.0 * dt / (24.0 * t + 4.0 * dt);
         u.c1 = u.cc[0];
@@ -721,7 +734,7 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     }
 
     // fast-path coefficients of both stages
-    h->h1 = d->dt / 6.0;
+    h->h1 = p.t2 ? 0.5 * d->dt : d->dt / 6.0;
     h->h2 = 5.0 * d->dt / 12.0;
     {
         const double dx = d->xf[1] - d->xf[0], dy = d->yf[1] - d->yf[0];
@@ -867,6 +880,21 @@ int dugks_step(dugks_t *h, int nsteps)
     for (int s = 0; s < nsteps; s++) {
         void *X = h->state[h->cur], *Y = h->state[1 - h->cur];
         int rc;
+        if (h->p.t2) {
+            // T2S3: one stage-A-shaped sweep from ftilde(t_n) to ftilde(t_n + dt)
+            if ((rc = record(h, KC_STAGE_A, true))) return rc;
+            if (h->lat) {
+                HIPCHECK(lattice_stage(h, 0, X, nullptr, Y));
+            } else {
+                LQStage a = lq_args(h, 0, X, nullptr, Y);
+                HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
+                // the cell reduction wrote the moments of Y into the stage-output slot
+                std::swap(h->mom_state, h->mom_G);
+            }
+            if ((rc = record(h, KC_STAGE_A, false))) return rc;
+            h->cur = 1 - h->cur;
+            continue;
+        }
         if ((rc = record(h, KC_STAGE_A, true))) return rc;
         if (h->lat) {
             HIPCHECK(lattice_stage(h, 0, X, nullptr, h->G));
@@ -953,7 +981,7 @@ int dugks_set_tau(dugks_t *h, const double *tau, int mem)
     } else {
         memcpy(host.data(), tau, sizeof(double) * n);
     }
-    int rc = check_tau(host.data(), (long long)n, 0, h->p.dt);
+    int rc = check_tau(host.data(), (long long)n, 0, h->p.dt, h->p.t2 != 0);
     if (rc) return rc;
     HIPCHECK(hipMemcpyAsync((void *)h->p.tau, host.data(), sizeof(double) * n, hipMemcpyHostToDevice,
                             h->stream));
@@ -1041,9 +1069,11 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
 {
     if (!out || !descs || n < 1) return fail(DUGKS_EINVAL, "bad arguments");
     *out = nullptr;
-    for (int k = 0; k < n; k++)
+    for (int k = 0; k < n; k++) {
         if (descs[k].precision != descs[0].precision || descs[k].stream != descs[0].stream)
             return fail(DUGKS_EINVAL, "instances of a batch share precision and stream");
+        if (descs[k].scheme != DUGKS_SCHEME_T3S3) return fail(DUGKS_EINVAL, "batches run the T3S3 scheme");
+    }
     dugks *h = new dugks();
     h->stream = (hipStream_t)descs[0].stream;
     h->delta = descs[0].precision == DUGKS_FP32_DELTA;
@@ -1323,6 +1353,7 @@ int dugks_backward(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
     if (!h || !f0 || !dL_du || !dL_df0 || nsteps < 0 || ckpt_every < 1)
         return fail(DUGKS_EINVAL, "bad arguments");
     if (h->batch) return fail(DUGKS_ENOTSUP, "backward of a batch handle");
+    if (h->p.t2) return fail(DUGKS_ENOTSUP, "the adjoint is written for the T3S3 scheme");
     const SweepParams &p = h->p;
     if (!p.perx || !p.pery || !p.uniform)
         return fail(DUGKS_ENOTSUP, "the adjoint supports periodic uniform grids only");

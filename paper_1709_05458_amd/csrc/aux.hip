@@ -51,6 +51,10 @@ __device__ void cell_moments(const SweepParams &p, const S *x, long long cell, d
     }
 }
 
+// The stored state is f - (dt/m) Omega(f) = f + dt/(m tau) (f - E): m = 4 for
+// T3S3 (fhat, eq. feqIntD3rdHat2 definitions), 2 for T2S3 (ftilde, Remark I).
+__device__ __forceinline__ double state_m(const SweepParams &p) { return p.t2 ? 2.0 : 4.0; }
+
 template <class S, bool DELTA>
 __global__ void k_set_state(const SweepParams p, const double *__restrict__ f, S *__restrict__ x)
 {
@@ -66,7 +70,7 @@ __global__ void k_set_state(const SweepParams p, const double *__restrict__ f, S
     }
     const double ux = mx / rho, uy = my / rho;
     const double tau = p.tau_field ? p.tau[cell] : p.tau0;
-    const double k = p.dt / (4.0 * tau);
+    const double k = p.dt / (state_m(p) * tau);
     for (int q = 0; q < p.nq; q++) {
         const double v = f[q * n + cell];
         const double e = p.w[q] * rho * eq_poly(p, q, ux, uy);
@@ -88,7 +92,8 @@ __global__ void k_get_state(const SweepParams p, const S *__restrict__ x, double
         const double fh = to_phys<DELTA>(p, q, (double)x[q * n + cell]);
         if (physical) {
             const double e = p.w[q] * rho * eq_poly(p, q, ux, uy);
-            f[q * n + cell] = (4.0 * tau * fh + p.dt * e) / (4.0 * tau + p.dt);
+            const double mt = state_m(p) * tau;
+            f[q * n + cell] = (mt * fh + p.dt * e) / (mt + p.dt);
         } else {
             f[q * n + cell] = fh;
         }
@@ -116,7 +121,7 @@ __global__ void k_init_eq(const SweepParams p, const double *__restrict__ rho,
     }
     const double uf = mfx / rf, vf = mfy / rf;
     const double tau = p.tau_field ? p.tau[cell] : p.tau0;
-    const double k = p.dt / (4.0 * tau);
+    const double k = p.dt / (state_m(p) * tau);
     for (int q = 0; q < p.nq; q++) {
         const double P = eq_poly(p, q, u, v);
         const double Pf = eq_poly(p, q, uf, vf);

@@ -21,14 +21,41 @@ struct Geometry {
 struct UniformCoef {
     double cc[2], ce[2];        // pre-reconstruction transform of stage A / C
     double c1, e1;              // fbar^{+,dt/6} = c1 fhat + e1 E
+    double kx0, ke0, aL0;       // stage A output: kx0 X + ke0 E + aL0 L
     double a_f, a_En, a_G, a_Ep;   // stage C own-cell combination
     double alpha[2], beta[2];   // interface recovery of stage A / C
 };
+
+// Stage-A coefficients of one cell: B = cc X + ce E before the reconstruction,
+// output kx X + ke E + aL L.  T3S3 (state fhat): B = fbar^{+,dt/6} (eq.
+// f_bar_1_6), output tilde f(t') = 5/4 B - 1/4 fhat + dt/3 L* (eq.
+// f_tilde_1_3 and Step 2).  T2S3 (state ftilde, Remark I with step dt):
+// B = fbar^{+,dt/2}, output ftilde^+ + dt L.
+struct Stage0Coef {
+    double cc, ce, kx, ke;
+};
+__host__ __device__ inline Stage0Coef stage0_coef(bool t2, double tau, double dt)
+{
+    Stage0Coef c;
+    if (t2) {
+        c.cc = (4.0 * tau - dt) / (4.0 * tau + 2.0 * dt);
+        c.ce = 3.0 * dt / (4.0 * tau + 2.0 * dt);
+        c.kx = (2.0 * tau - dt) / (2.0 * tau + dt);
+        c.ke = 2.0 * dt / (2.0 * tau + dt);
+    } else {
+        c.cc = (12.0 * tau - dt) / (12.0 * tau + 3.0 * dt);
+        c.ce = 4.0 * dt / (12.0 * tau + 3.0 * dt);
+        c.kx = 1.25 * c.cc - 0.25;
+        c.ke = 1.25 * c.ce;
+    }
+    return c;
+}
 
 // Everything a sweep kernel needs; passed by value as a kernel argument.
 struct SweepParams {
     int nx, ny;
     long long ncell;
+    int t2;                  // scheme T2S3 (one stage-A-shaped step, state ftilde)
     int perx, pery;          // periodic in x / y
     int uniform;             // uniform spacing in both directions
     int nq;

@@ -319,9 +319,10 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
         if (!p.tau_field) {
             cc = p.uc.cc[STAGE];
             ce = p.uc.ce[STAGE];
-        } else if (STAGE == 0) {   // eq. f_bar_1_6
-            cc = (12.0 * tau - dt) / (12.0 * tau + 3.0 * dt);
-            ce = 4.0 * dt / (12.0 * tau + 3.0 * dt);
+        } else if (STAGE == 0) {   // eq. f_bar_1_6 (T3S3) or fbar^{+,dt/2} of Remark I (T2S3)
+            const Stage0Coef c0 = stage0_coef(p.t2, tau, dt);
+            cc = c0.cc;
+            ce = c0.ce;
         } else {   // eq. fbp_5_12 with the coefficients that map tilde f onto fbar^{+,5dt/12}
             cc = (24.0 * tau - 5.0 * dt) / (24.0 * tau + 4.0 * dt);
             ce = 9.0 * dt / (24.0 * tau + 4.0 * dt);
@@ -340,10 +341,17 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
         if (c == tid && valid) {
             o_rho = rho;
             if (STAGE == 0) {
-                // tilde f^+(t_n) = 5/4 fbar^{+,dt/6} - 1/4 fhat  (eq. f_tilde_1_3)
+                // T3S3: tilde f^+(t_n) = 5/4 fbar^{+,dt/6} - 1/4 fhat  (eq. f_tilde_1_3);
+                // T2S3: ftilde^+ = ((2 tau - dt) ftilde + 2 dt E) / (2 tau + dt)
+                double kxd = p.uc.kx0, ked = p.uc.ke0;
+                if (p.tau_field) {
+                    const Stage0Coef c0 = stage0_coef(p.t2, tau_o, dt);
+                    kxd = c0.kx;
+                    ked = c0.ke;
+                }
                 EPolyS<S> en;
-                en.set(ep_cell, 1.25 * e1 - rounding_of<S>(1.25 * c1 - 0.25));
-                const S kx = (S)(1.25 * c1 - 0.25);
+                en.set(ep_cell, ked - rounding_of<S>(kxd));
+                const S kx = (S)kxd;
                 [&]<int... qs>(std::integer_sequence<int, qs...>) {
                     ((t.R[qs] = fmaS(kx, v[qs],
                                      DELTA ? en.template eval<Lat::ex(qs), Lat::ey(qs)>()
@@ -390,7 +398,7 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
     }
     __syncthreads();
     if (!valid) return;   // no further barrier below
-    const S aL = (S)(STAGE == 0 ? dt / 3.0 : 4.0 * dt / 7.0);
+    const S aL = (S)(STAGE == 0 ? p.uc.aL0 : 4.0 * dt / 7.0);
 
     // ---- interface recovery weights of the four faces (eq. recover2f) -------
     double tb[4];

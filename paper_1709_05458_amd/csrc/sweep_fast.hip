@@ -191,8 +191,9 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
         } else {
             const double tau = has[s] ? p.tau[cell[s]] : p.tau0;
             if (STAGE == 0) {
-                cc = (12.0 * tau - dt) / (12.0 * tau + 3.0 * dt);
-                ce = 4.0 * dt / (12.0 * tau + 3.0 * dt);
+                const Stage0Coef c0 = stage0_coef(p.t2, tau, dt);
+                cc = c0.cc;
+                ce = c0.ce;
             } else {
                 cc = (24.0 * tau - 5.0 * dt) / (24.0 * tau + 4.0 * dt);
                 ce = 9.0 * dt / (24.0 * tau + 4.0 * dt);
@@ -236,11 +237,18 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
     S R0[Q];
     EPoly EO;   // equilibrium terms of the output (storage units), before the flux part is added
     if (STAGE == 0) {
-        // tilde f^+(t_n) = 5/4 fbar^{+,dt/6} - 1/4 fhat (eq. f_tilde_1_3)
-        const S kx = (S)(1.25 * c1 - 0.25);
+        // T3S3: tilde f^+(t_n) = 5/4 fbar^{+,dt/6} - 1/4 fhat (eq. f_tilde_1_3);
+        // T2S3: ftilde^+ = ((2 tau - dt) ftilde + 2 dt E) / (2 tau + dt)
+        double kxd = p.uc.kx0, ked = p.uc.ke0;
+        if (TF) {
+            const Stage0Coef c0 = stage0_coef(p.t2, tau_o, dt);
+            kxd = c0.kx;
+            ked = c0.ke;
+        }
+        const S kx = (S)kxd;
 #pragma unroll
         for (int q = 0; q < Q; q++) R0[q] = kx * v[0][q];
-        const double k = 1.25 * e1 - rounding_of<S>(1.25 * c1 - 0.25);
+        const double k = ked - rounding_of<S>(kxd);
         EO = {ep_own.c0 * k, ep_own.c1x * k, ep_own.c1y * k, ep_own.c2xx * k, ep_own.c2xy * k, ep_own.c2yy * k};
     } else {
         // fhat(t_{n+1}) = a_f fhat + a_G tilde f(t') + a_En E^n + a_Ep E' + 4dt/7 L**
@@ -341,7 +349,7 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
         phys_moments(p, DELTA, mr[k], mx[k], my[k], rho, drho, mxx, myy);
         ef[k] = epoly(rho, drho, mxx, myy, p.iRT, cl, DELTA);
     }
-    const double aL = STAGE == 0 ? dt / 3.0 : 4.0 * dt / 7.0;
+    const double aL = STAGE == 0 ? p.uc.aL0 : 4.0 * dt / 7.0;
     const double kx = -p.inv_dx * cl * aL, ky = -p.inv_dy * cl * aL;
     const double A0 = beta[1] * ef[1].c0 - beta[0] * ef[0].c0, A1 = beta[1] * ef[1].c1x - beta[0] * ef[0].c1x,
                  A2 = beta[1] * ef[1].c1y - beta[0] * ef[0].c1y, A3 = beta[1] * ef[1].c2xx - beta[0] * ef[0].c2xx,

@@ -44,8 +44,9 @@ __device__ __forceinline__ void stage_transform(const SweepParams &p, int stage,
     }
     const double tau = p.tau[cell], dt = p.dt;
     if (stage == 0) {
-        cc = (12.0 * tau - dt) / (12.0 * tau + 3.0 * dt);
-        ce = 4.0 * dt / (12.0 * tau + 3.0 * dt);
+        const Stage0Coef c0 = stage0_coef(p.t2, tau, dt);
+        cc = c0.cc;
+        ce = c0.ce;
     } else {
         cc = (24.0 * tau - 5.0 * dt) / (24.0 * tau + 4.0 * dt);
         ce = 9.0 * dt / (24.0 * tau + 4.0 * dt);
@@ -656,12 +657,19 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int block
         const EPoly ex = epoly(mx[0], mx[1], mx[2], mx[3], p.iRT, 1.0, DELTA);
         double EO[6], aLd;
         if (a.stage == 0) {
-            // tilde f^+(t_n) = (5/4 c1 - 1/4) fhat + 5/4 e1 E^n (eq. f_tilde_1_3)
-            const double k = 1.25 * e1 - rounding_of<S>(1.25 * c1 - 0.25);
+            // T3S3: tilde f^+(t_n) = (5/4 c1 - 1/4) fhat + 5/4 e1 E^n (eq. f_tilde_1_3);
+            // T2S3: ftilde^+ = ((2 tau - dt) ftilde + 2 dt E) / (2 tau + dt)
+            double kxd = p.uc.kx0, ked = p.uc.ke0;
+            if (p.tau_field) {
+                const Stage0Coef c0 = stage0_coef(p.t2, tau_o, dt);
+                kxd = c0.kx;
+                ked = c0.ke;
+            }
+            const double k = ked - rounding_of<S>(kxd);
             EO[0] = k * ex.c0; EO[1] = k * ex.c1x; EO[2] = k * ex.c1y;
             EO[3] = k * ex.c2xx; EO[4] = k * ex.c2xy; EO[5] = k * ex.c2yy;
-            kx_own = (S)(1.25 * c1 - 0.25);
-            aLd = dt / 3.0;
+            kx_own = (S)kxd;
+            aLd = p.uc.aL0;
         } else {
             double a_f = p.uc.a_f, a_En = p.uc.a_En, a_G = p.uc.a_G, a_Ep = p.uc.a_Ep;
             if (p.tau_field) {

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdugks.so")
 
 FP64, FP32_DELTA = 0, 1
+T3S3, T2S3 = 0, 1   # time integrators (dugks_scheme)
 MEM_HOST, MEM_DEVICE = 0, 1
 ALLOW_MOMENT_DEFECT = 1
 FORCE_GENERIC = 2
@@ -41,7 +42,8 @@ class DugksDesc(ctypes.Structure):
                 ("bc", c_int * 4), ("u_wall", (c_double * 2) * 4),
                 ("precision", c_int), ("rho0", c_double), ("taylor_quad", c_double),
                 ("stream", c_void_p), ("flags", c_int),
-                ("tile_x", c_int), ("tile_y", c_int)]
+                ("tile_x", c_int), ("tile_y", c_int),
+                ("scheme", c_int)]
 
 
 _lib = None
@@ -121,7 +123,7 @@ def _default_stream():
 
 
 def make_desc(case, precision=FP64, taylor_quad=1.0, stream=None, tile=None, allow_defect=False,
-              tau=None, force_generic=False, d=None):
+              tau=None, force_generic=False, d=None, scheme=T3S3):
     """Fill a DugksDesc from a cases.Case; returns (desc, arrays to keep alive)."""
     g, vs = case.grid, case.vs
     keep = [np.ascontiguousarray(g.xf, dtype=np.float64),
@@ -155,15 +157,16 @@ def make_desc(case, precision=FP64, taylor_quad=1.0, stream=None, tile=None, all
     d.flags = (ALLOW_MOMENT_DEFECT if allow_defect else 0) | (FORCE_GENERIC if force_generic else 0)
     if tile:
         d.tile_x, d.tile_y = tile
+    d.scheme = scheme
     return d, keep
 
 
 class Solver:
-    """One T3S3-DUGKS solver instance (a dugks_t handle)."""
+    """One DUGKS solver instance (a dugks_t handle); scheme T3S3 (default) or T2S3."""
 
     def __init__(self, case, precision: int = FP64, taylor_quad: float = 1.0, stream=None,
                  tile=None, allow_defect: bool = False, tau=None, force_generic: bool = False,
-                 tau_field: bool = False, _borrowed=None):
+                 tau_field: bool = False, scheme: int = T3S3, _borrowed=None):
         g, vs = case.grid, case.vs
         self.case = case
         self.nx, self.ny, self.nq = g.nx, g.ny, vs.nq
@@ -212,6 +215,7 @@ class Solver:
         d.flags = (ALLOW_MOMENT_DEFECT if allow_defect else 0) | (FORCE_GENERIC if force_generic else 0)
         if tile:
             d.tile_x, d.tile_y = tile
+        d.scheme = scheme
         self.desc = d
         h = c_void_p()
         check(lib().dugks_create(byref(d), byref(h)), "dugks_create")
@@ -384,7 +388,7 @@ class BatchSolver:
     """Many independent instances stepped together (dugks_create_batch)."""
 
     def __init__(self, cases, precision: int = FP32_DELTA, tiles=None, stream=None,
-                 allow_defect=None, taylor_quad: float = 1.0):
+                 allow_defect=None, taylor_quad: float = 1.0, scheme: int = T3S3):
         n = len(cases)
         descs = (DugksDesc * n)()
         self._keep = []
@@ -392,7 +396,7 @@ class BatchSolver:
         for k, c in enumerate(cases):
             allow = (abs(c.vs.moment_defect()["sum_w_minus_1"]) > 1e-10) if allow_defect is None else allow_defect
             _, keep = make_desc(c, precision, taylor_quad, stream, tiles[k] if tiles else None, allow,
-                                d=descs[k])
+                                d=descs[k], scheme=scheme)
             self._keep.append(keep)
         self._descs = descs
         h = c_void_p()

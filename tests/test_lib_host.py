@@ -66,6 +66,8 @@ def test_descriptor_validation_on_the_host():
     vs.w[0], vs.w[8] = vs.w[0] * 1.1, vs.w[8] * 0.9
     bb = C.cavity_case(16, vs, tau=0.1)
     _expect(-1, bb)
+    # an unknown time integrator
+    _expect(-1, C.tgv_case(16), scheme=7)
     # FP32-delta storage needs a reference density
     c2 = C.tgv_case(16)
     c2.rho0 = 0.0
