@@ -32,11 +32,11 @@ namespace dk {
 // x / y interface values of the four faces of the own cell from the window
 // weights of one velocity (uniform spacing; upwind choice, foot point and
 // 3-point derivatives folded into the weights), their moments in double,
-// and the linear flux part.
+// and the linear flux part (added to R with its factor aLs).
 template <class Lat, class S, bool DELTA, bool TF, int q, int HX, int PL>
 __device__ __forceinline__ void fast_faces(const SweepParams &p, const S *lds, const S *__restrict__ C,
                                            double (&mr)[4], double (&mx)[4], double (&my)[4], const S (&kxm)[4],
-                                           const S (&kym)[4], const S (&al)[4], S &La)
+                                           const S (&kym)[4], const S (&al)[4], S aLs, S &R)
 {
     constexpr int EX = Lat::ex(q), EY = Lat::ey(q), SH = Lat::shell(q);
     const S *P = lds + q * PL;
@@ -87,7 +87,7 @@ __device__ __forceinline__ void fast_faces(const SweepParams &p, const S *lds, c
         const S dyv = TF ? fmaS(al[3], vn, -al[2] * vs) : vn - vs;
         l = fmaS(ky, dyv, l);
     }
-    La = l;
+    R = fmaS(aLs, l, R);   // the flux part joins the own-cell part at once
     // keep the next velocity's loads below this one (register pressure)
     __builtin_amdgcn_sched_barrier(0);
 }
@@ -331,11 +331,11 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
 
     // ---- interface values, moments, linear flux part -------------------------
     double mr[4] = {0, 0, 0, 0}, mx[4] = {0, 0, 0, 0}, my[4] = {0, 0, 0, 0};
-    S La[Q];
+    const S aLs = (S)(STAGE == 0 ? p.uc.aL0 : 4.0 * dt / 7.0);
     {
         const S *base = lds + (ly + 2) * HX + (lx + 2);
         [&]<int... qs>(std::integer_sequence<int, qs...>) {
-            (fast_faces<Lat, S, DELTA, TF, qs, HX, PS>(p, base, coef + qs * 24, mr, mx, my, kxm, kym, al, La[qs]),
+            (fast_faces<Lat, S, DELTA, TF, qs, HX, PS>(p, base, coef + qs * 24, mr, mx, my, kxm, kym, al, aLs, R0[qs]),
              ...);
         }(Seq{});
     }
@@ -363,13 +363,12 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
     const S m_xx = (S)(EO.c2xx + kx * A1), m_xy = (S)(EO.c2xy + kx * A2 + ky * B1), m_yy = (S)(EO.c2yy + ky * B2);
     const S m_xxx = (S)(kx * A3), m_xxy = (S)(kx * A4 + ky * B3), m_xyy = (S)(kx * A5 + ky * B4),
             m_yyy = (S)(ky * B5);
-    const S aLs = (S)aL;
     const size_t no = (size_t)p.ncell_o;
     const unsigned oc = (unsigned)ocell;
     // M at e and -e (velocities q and opp(q)) from its even (m0 and quadratic)
     // and odd (linear and cubic) parts
     auto store = [&](int q, S M, S wq) {
-        const S r = fmaS(aLs, La[q], R0[q]);
+        const S r = R0[q];
         *(S *)((char *)(out + (size_t)q * no) + (unsigned)(sizeof(S) * oc)) = DELTA ? r + M : fmaS(wq, M, r);
     };
     [&]<int... qs>(std::integer_sequence<int, qs...>) {
