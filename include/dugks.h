@@ -106,9 +106,9 @@ typedef struct {
     void *stream;           /* hipStream_t for all work, NULL = null stream */
     int flags;              /* dugks_flags */
     int tile_x, tile_y;     /* sweep tile in cells; 0 = library choice */
-    int scheme;             /* dugks_scheme; 0 = T3S3.  T2S3 has no dt/tau bound
-                             * (its relaxation factor stays in (-1, 1)); dugks_backward
-                             * and batches take T3S3 only (DUGKS_ENOTSUP / DUGKS_EINVAL) */
+    int scheme;             /* dugks_scheme; 0 = T3S3.  Both schemes take the
+                             * dt/tau <= 12 guard; dugks_backward and batches take
+                             * T3S3 only (DUGKS_ENOTSUP / DUGKS_EINVAL) */
 } dugks_desc;
 
 /* Build a solver for one grid / velocity set / relaxation field (paper:

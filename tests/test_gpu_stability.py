@@ -1,0 +1,61 @@
+"""The paper's stability study (lid-driven cavity, Re = 100, 25 x 25 cells):
+T3S3 runs to a steady state for dt/tau just under its bound of 12 (Sec. on the
+time discretisation's von Neumann analysis, and the cavity figure of maximum
+dt/tau).  The lid speed is set from tau so that Re = U L / nu stays 100 for
+every dt/tau.  T2S3 is held to the same guard and is steady there at CFL 0.75.
+
+Steady means the change of u over 1000 steps, relative to u, falls below the
+bar; the run also has to conserve mass (bounce-back walls) and keep u finite.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1709_05458_amd import cases as C
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():   # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1709_05458_amd import dugks  # noqa: E402
+
+
+def _cavity_re100(n, cfl, dt_over_tau):
+    vs = C.d2q9(1.0 / 3.0)
+    dt = cfl * (1.0 / n) / vs.cmax
+    tau = dt / dt_over_tau
+    U = 100.0 * tau * vs.RT          # Re = U / (tau RT) = 100 on the unit square
+    return C.cavity_case(n, vs, re=100.0, cfl=cfl, tau=tau, lid=U), U
+
+
+@pytest.mark.parametrize("scheme,cfl,ratio,bar", [
+    (dugks.T3S3, 1.0, 11.5, 1e-10),   # measured 1.8e-14
+    (dugks.T3S3, 0.5, 11.5, 1e-5),    # measured 2.0e-6 (smaller steps, slower approach)
+    (dugks.T2S3, 0.75, 12.0, 1e-9),   # measured 5.6e-12
+])
+def test_cavity_re100_steady_near_the_dt_over_tau_bound(scheme, cfl, ratio, bar):
+    case, U = _cavity_re100(25, cfl, ratio)
+    name = "T3S3" if scheme == dugks.T3S3 else "T2S3"
+    print(f"[gpu] cavity Re 100 25x25 {name} CFL {cfl} dt/tau {ratio}", file=sys.stderr, flush=True)
+    s = dugks.Solver(case, dugks.FP64, scheme=scheme)
+    s.init_equilibrium(case.rho, case.ux, case.uy)
+    m0 = s.moments()[0].sum()
+    prev = None
+    for _ in range(20):
+        s.step(1000)
+        s.sync()
+        r, ux, uy = s.moments()
+        assert np.isfinite(ux).all() and np.isfinite(uy).all()
+        if prev is not None:
+            res = np.sqrt(((ux - prev[0]) ** 2 + (uy - prev[1]) ** 2).sum() / (ux ** 2 + uy ** 2).sum())
+        prev = (ux, uy)
+    print(f"    residual {res:.2e}  max|u|/U {np.abs(ux).max() / U:.3f}", file=sys.stderr, flush=True)
+    assert res < bar
+    assert abs(r.sum() - m0) < 1e-10 * m0
+    # the primary vortex: the top row follows the lid, the flow below it returns
+    assert 0.8 < ux[-1].max() / U < 0.95
+    assert ux[: case.grid.ny // 2].min() < -0.05 * U
+    s.close()

@@ -105,13 +105,15 @@ def test_t2s3_fp32_delta_against_fp64_oracle(name):
     s.close()
 
 
-def test_t2s3_has_no_dt_over_tau_bound_and_conserves():
-    # dt/tau = 20: beyond the T3S3 bound of 12 (refused there), fine for T2
+def test_t2s3_takes_the_dt_over_tau_guard_and_conserves():
+    # the whole T2S3 step is bounded too (cavity: dt/tau = 9 at CFL 1), so it
+    # shares the T3S3 guard of 12
     case = _mk("tgv32_d2q9")
-    case.tau = np.full_like(case.tau, case.dt / 20.0)
+    case.tau = np.full_like(case.tau, case.dt / 12.5)
     with pytest.raises(dugks.DugksError) as e:
-        dugks.Solver(case, dugks.FP64)
+        dugks.Solver(case, dugks.FP64, scheme=dugks.T2S3)
     assert e.value.code == -2
+    case.tau = np.full_like(case.tau, case.dt / 12.0)
     o, s, ft0 = _pair(case)
     want = o.t2_step(ft0, case.dt)
     r0, u0, v0 = s.moments()
