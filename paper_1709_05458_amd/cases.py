@@ -413,6 +413,40 @@ def cavity_case(n: int, vs: VelocitySet | None = None, re: float = 400.0,
                 1.0, steps, {"U": U, "Re": re})
 
 
+def shear_layer_fields(xc, yc, k: float = 80.0, delta: float = 0.05, U: float = 1.0):
+    """Doubly periodic shear layers on [0,1]^2 (paper's shear-layer section):
+    u_x = U tanh(k (y - 1/4)) for y <= 1/2 and U tanh(k (3/4 - y)) above,
+    u_y = U delta sin(2 pi (x + 1/4)); rho = 1.  Shape (ny, nx)."""
+    X, Y = np.meshgrid(xc, yc)
+    ux = U * np.where(Y <= 0.5, np.tanh(k * (Y - 0.25)), np.tanh(k * (0.75 - Y)))
+    uy = U * delta * np.sin(2.0 * math.pi * (X + 0.25))
+    return np.ones_like(X), ux, uy
+
+
+def shear_layer_case(n: int = 128, vs: VelocitySet | None = None, k: float = 80.0,
+                     delta: float = 0.05, nu: float = 1e-4, U: float = 1.0, ma: float = 0.15,
+                     dt_over_tau: float = 10.0, t_end: float = 1.0) -> Case:
+    """The paper's shear-layer workload: k = 80, delta = 0.05, nu = 1e-4
+    (Re = U L / nu = 10^4), periodic, n x n uniform cells on [0,1]^2.
+
+    The paper gives neither the lattice temperature nor the step.  RT follows
+    from Ma = U / sqrt(3 RT) (0.15, the paper's cavity Mach number), tau =
+    nu / RT, and dt = dt_over_tau * tau, below the bound of 12; the CFL
+    number dt C / dx is then far below 1 at these sizes.  steps reaches
+    t_end."""
+    RT = (U / ma) ** 2 / 3.0
+    vs = vs if vs is not None else d2q9(RT)
+    g = uniform_grid(n, n)
+    tau0 = nu / vs.RT
+    dt = dt_over_tau * tau0
+    if dt * vs.cmax > g.dmin:
+        raise ValueError("CFL number above 1 for this size; lower dt_over_tau")
+    rho, ux, uy = shear_layer_fields(g.xc, g.yc, k, delta, U)
+    return Case(f"shear{n}_{vs.name}", g, vs, dt, np.full((n, n), tau0),
+                (BC_PERIODIC,) * 4, np.zeros((4, 2)), rho, ux, uy, 1.0,
+                int(round(t_end / dt)), {"U": U, "k": k, "delta": delta, "nu": nu, "Ma": ma})
+
+
 def couette_case(n: int, vs: VelocitySet, tau: float, U: float, cfl: float = 0.25,
                  grid: Grid | None = None, steps: int = 1000) -> Case:
     """Planar Couette flow: periodic in x, diffuse walls at y = 0 and y = 1

@@ -335,6 +335,27 @@ def test_rotation_symmetry_of_the_noise_free_taylor_green_vortex():
     assert np.abs(r[i, N - 1 - j] - r[j, i]).max() < 1e-14
 
 
+def test_shear_layer_keeps_its_reflection_symmetry():
+    # The doubly periodic shear layers (paper's shear-layer section) are
+    # invariant under (x, y) -> (x + 1/2, 1 - y) with (u_x, u_y) -> (u_x, -u_y):
+    # a half-period shift in x with a mirror in y.  D2Q9 is closed under
+    # xi_y -> -xi_y, so the discrete solution keeps it to round-off; a swapped
+    # axis or a wrong sign of a y term would not.
+    N = 32
+    case = C.shear_layer_case(N, k=20.0)
+    o = oracle.Oracle(case)
+    fh = o.run(o.init_fhat(), 30)
+    r, ux, uy = o.moments(fh)
+    assert np.abs(uy).max() > 0.04      # the perturbation is present
+    T = lambda a: np.roll(a[::-1, :], -N // 2, axis=1)
+    assert np.abs(ux - T(ux)).max() < 1e-13
+    assert np.abs(uy + T(uy)).max() < 1e-13
+    assert np.abs(r - T(r)).max() < 1e-13
+    # and not a symmetry the state has for another reason: the flow along x
+    # breaks the plain mirror x -> 1 - x
+    assert np.abs(uy - uy[:, ::-1]).max() > 1e-3
+
+
 def _tv_error(N, steps, literal=True, nu=0.01, dt=1e-5, dt_over_tau=4.0):
     tau = dt / dt_over_tau
     RT = nu / tau
