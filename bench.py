@@ -80,9 +80,10 @@ def parse():
     ap.add_argument("--scheme", default="t3s3", choices=["t3s3", "t2s3"],
                     help="time integrator of the Taylor-Green workload (t2s3: the paper's second-order "
                          "comparison scheme, one sweep per step)")
-    ap.add_argument("--workload", default="tgv", choices=["tgv", "batched", "rarefied"],
+    ap.add_argument("--workload", default="tgv", choices=["tgv", "batched", "rarefied", "adjoint"],
                     help="tgv: Taylor-Green (headline); batched: 64 uneven cavities in one graph "
-                         "launch per step; rarefied: Newton-Cotes cavity on stretched cells")
+                         "launch per step; rarefied: Newton-Cotes cavity on stretched cells; adjoint: "
+                         "gradient of 500 Taylor-Green 256^2 D2Q9 steps (dugks_backward)")
     ap.add_argument("--nc", type=int, default=101, help="Newton-Cotes points per axis (rarefied)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
@@ -210,30 +211,101 @@ def run_rarefied(args):
     case = C.cavity_case(n, vs, wall=C.BC_DIFFUSE, grid=C.tanh_grid(n, n), tau=C.kn_to_tau(1.0, 0.5),
                          lid=0.146, cfl=0.25)
     out = {}
-    for prec, name in ((dugks.FP32_DELTA, "fp32"), (dugks.FP64, "fp64")):
+    pairs = n * n * vs.nq
+    steps = max(3, args.steps // 10)
+    for prec, name, elem in ((dugks.FP32_DELTA, "fp32", 4), (dugks.FP64, "fp64", 8)):
         s = dugks.Solver(case, prec, allow_defect=True)
         s.init_equilibrium(case.rho, case.ux, case.uy)
         s.step(2)
         s.sync()
-        steps = max(3, args.steps // 10)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         s.step(steps)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
-        pairs = n * n * vs.nq
+        # kernel times in a run of their own: while profiling, each stage's
+        # faces and update kernels are timed separately
+        s.prof_begin(4 * steps + 8)
+        s.step(steps)
+        f_ms, f_n = s.prof_query(dugks.K_LQ_FACES)
+        u_ms, u_n = s.prof_query(dugks.K_LQ_UPDATE)
+        s.prof_end()
+        s.sync()
+        # algorithmic bytes of the faces kernel: it reads the stage input and
+        # writes the x- and y-face values, about three stored elements per pair
+        faces_gbs = 3 * elem * pairs / (f_ms * 1e-3) / 1e9
         out[name] = {"value": round(pairs / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 4),
-                     "variant": s.describe()}
+                     "variant": s.describe(), "faces_ms": round(f_ms, 5), "update_ms": round(u_ms, 5),
+                     "launches": (f_n, u_n), "faces_GBs": round(faces_gbs, 1),
+                     "faces_frac": round(faces_gbs / HBM_PEAK_GBS, 4)}
         s.close()
+    r = out["fp32"]
     return {"metric": METRIC,
-            "value": out["fp32"]["value"], "unit": UNIT, "n_gpus": 1,
-            "steps": max(3, args.steps // 10), "warmup": 2, "ms_per_step": out["fp32"]["ms_per_step"],
+            "value": r["value"], "unit": UNIT, "n_gpus": 1,
+            "steps": steps, "warmup": 2, "ms_per_step": r["ms_per_step"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": f"rarefied cavity {n}x{n} tanh cells, Newton-Cotes {args.nc}x{args.nc}, "
-                                   "Kn 1, diffuse walls"},
-            "fp64": out["fp64"], "roofline": None, "cpu_baseline": None}
+                                   "Kn 1, diffuse walls",
+                       "pairs": pairs, "variant": r["variant"]},
+            "fp64": out["fp64"],
+            "roofline": {"bound": "hbm", "kernel": "lq_faces (any-size faces kernel, both stages)",
+                         "achieved": r["faces_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": r["faces_frac"], "traffic": None, "bytes_per_launch": 3 * 4 * pairs,
+                         "launch_ms": r["faces_ms"], "update_ms": r["update_ms"]},
+            "cpu_baseline": None}
+
+
+def run_adjoint(args):
+    """Gradient of ||u(T)||^2 after 500 T3S3 steps of the Taylor-Green vortex
+    (256^2, D2Q9, per-cell tau field, FP32-delta forward, FP64 adjoint) with
+    respect to the initial f and the tau field, checkpoint every 25 steps
+    (dugks_backward).  Inputs and outputs stay in device memory."""
+    import torch
+    from paper_1709_05458_amd import cases as C, dugks
+    n, nsteps, ckpt = 256, 500, 25
+    case = C.tgv_case(n, C.d2q9(1.0 / 3.0))
+    s = dugks.Solver(case, dugks.FP32_DELTA, tau_field=True)
+    s.init_equilibrium(case.rho, case.ux, case.uy)
+    dev = torch.device("cuda", 0)
+    f0 = torch.from_numpy(s.get_state()).to(dev)
+    s.step(nsteps)
+    _, ux, uy = s.moments()
+    seed = torch.from_numpy(2.0 * np.stack([ux, uy])).to(dev)
+    s.backward(f0, 50, ckpt, None, seed)   # warm-up (workspace, code paths)
+    torch.cuda.synchronize()
+    s.prof_begin(nsteps + 8)
+    t0 = time.perf_counter()
+    gf, gt = s.backward(f0, nsteps, ckpt, None, seed)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    a_ms, a_n = s.prof_query(dugks.K_ADJ_STEP)
+    s.prof_end()
+    finite = bool(torch.isfinite(gf).all().item() and torch.isfinite(gt).all().item())
+    desc = s.describe()
+    s.close()
+    pairs = n * n * case.vs.nq
+    # algorithmic bytes of one reverse step: read the adjoint state and write
+    # its predecessor (FP64), read the forward state and the stage-A output it
+    # linearises about (FP32-delta)
+    per_pair = 8 + 8 + 4 + 4
+    achieved = per_pair * pairs / (a_ms * 1e-3) / 1e9
+    ms = wall * 1e3 / nsteps
+    return {"metric": METRIC,
+            "value": round(pairs / (ms * 1e-3) / 1e9, 3), "unit": UNIT, "n_gpus": 1,
+            "steps": nsteps, "warmup": 1, "ms_per_step": round(ms, 5),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": "adjoint: taylor-green 256x256 D2Q9 with a tau field, 500 steps, checkpoint "
+                                   "every 25, FP32-delta forward and FP64 adjoint; value counts each step of "
+                                   "the backward call once (forward recompute included)",
+                       "pairs": pairs, "variant": desc, "gradients_finite": finite},
+            "roofline": {"bound": "hbm", "kernel": "one reverse step (adj_prep, adj_face x2, adj_cellC, adj_cellA)",
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                         "bytes_per_launch": per_pair * pairs, "launch_ms": round(a_ms, 5), "launches": a_n},
+            "cpu_baseline": None}
 
 
 def cpu_baseline(lattice):
@@ -273,6 +345,9 @@ def main():
         return
     if args.workload == "rarefied":
         print(json.dumps(run_rarefied(args)))
+        return
+    if args.workload == "adjoint":
+        print(json.dumps(run_adjoint(args)))
         return
     tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
     case = make_case(args.n, args.lattice)

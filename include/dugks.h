@@ -199,8 +199,19 @@ int dugks_batch_instance(dugks_t *h, int k, dugks_t **inst);
 /* Kernel timing by HIP events recorded around each launch on the stream.
  * prof_begin clears the record (room for max_launches launches); after the
  * stream is synchronised, prof_query returns the mean duration in ms and the
- * count of launches of one kernel class (dugks_kernel). */
-enum dugks_kernel { DUGKS_K_STAGE_A = 0, DUGKS_K_STAGE_C = 1, DUGKS_K_AUX = 2, DUGKS_K_COUNT = 3 };
+ * count of launches of one kernel class (dugks_kernel).
+ *   STAGE_A, STAGE_C: one stage of dugks_step on the lattice kernels (all of a
+ *     step for T2S3: STAGE_A);
+ *   AUX: one graph launch of a batch step;
+ *   LQ_FACES, LQ_UPDATE: the faces and the update kernel of one stage of the
+ *     any-size kernels (while profiling, those stages record these two
+ *     instead of STAGE_A / STAGE_C; the two reductions are not timed);
+ *   ADJ_STEP: one reverse step of dugks_backward (its five kernels: the
+ *     linearisation point, two face adjoints, two cell adjoints). */
+enum dugks_kernel {
+    DUGKS_K_STAGE_A = 0, DUGKS_K_STAGE_C = 1, DUGKS_K_AUX = 2,
+    DUGKS_K_LQ_FACES = 3, DUGKS_K_LQ_UPDATE = 4, DUGKS_K_ADJ_STEP = 5, DUGKS_K_COUNT = 6
+};
 int dugks_prof_begin(dugks_t *h, int max_launches);
 int dugks_prof_query(dugks_t *h, int kernel, double *mean_ms, int *count);
 int dugks_prof_end(dugks_t *h);

@@ -874,6 +874,27 @@ static int record(dugks *h, int kind, bool start)
     return DUGKS_OK;
 }
 
+// One stage of the any-size kernels.  While profiling, the faces and the
+// update kernel are timed on their own; otherwise the whole stage is one
+// STAGE_A / STAGE_C record.
+static int lq_stage(dugks *h, const LQStage &a)
+{
+    int rc;
+    if (!h->prof_on) {
+        HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
+        return DUGKS_OK;
+    }
+    if ((rc = record(h, KC_LQ_FACES, true))) return rc;
+    HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, 0));
+    if ((rc = record(h, KC_LQ_FACES, false))) return rc;
+    HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, 1));
+    if ((rc = record(h, KC_LQ_UPDATE, true))) return rc;
+    HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, 2));
+    if ((rc = record(h, KC_LQ_UPDATE, false))) return rc;
+    HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, 3));
+    return DUGKS_OK;
+}
+
 static int batch_step(dugks_t *h, int nsteps);
 
 int dugks_step(dugks_t *h, int nsteps)
@@ -883,39 +904,37 @@ int dugks_step(dugks_t *h, int nsteps)
     for (int s = 0; s < nsteps; s++) {
         void *X = h->state[h->cur], *Y = h->state[1 - h->cur];
         int rc;
+        const bool whole = h->lat || !h->prof_on;   // stage records (else per-kernel ones)
         if (h->p.t2) {
             // T2S3: one stage-A-shaped sweep from ftilde(t_n) to ftilde(t_n + dt)
-            if ((rc = record(h, KC_STAGE_A, true))) return rc;
+            if (whole && (rc = record(h, KC_STAGE_A, true))) return rc;
             if (h->lat) {
                 HIPCHECK(lattice_stage(h, 0, X, nullptr, Y));
             } else {
-                LQStage a = lq_args(h, 0, X, nullptr, Y);
-                HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
+                if ((rc = lq_stage(h, lq_args(h, 0, X, nullptr, Y)))) return rc;
                 // the cell reduction wrote the moments of Y into the stage-output slot
                 std::swap(h->mom_state, h->mom_G);
             }
-            if ((rc = record(h, KC_STAGE_A, false))) return rc;
+            if (whole && (rc = record(h, KC_STAGE_A, false))) return rc;
             h->cur = 1 - h->cur;
             continue;
         }
-        if ((rc = record(h, KC_STAGE_A, true))) return rc;
+        if (whole && (rc = record(h, KC_STAGE_A, true))) return rc;
         if (h->lat) {
             HIPCHECK(lattice_stage(h, 0, X, nullptr, h->G));
         } else {
-            LQStage a = lq_args(h, 0, X, nullptr, h->G);
-            HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
+            if ((rc = lq_stage(h, lq_args(h, 0, X, nullptr, h->G)))) return rc;
         }
-        if ((rc = record(h, KC_STAGE_A, false))) return rc;
-        if ((rc = record(h, KC_STAGE_C, true))) return rc;
+        if (whole && (rc = record(h, KC_STAGE_A, false))) return rc;
+        if (whole && (rc = record(h, KC_STAGE_C, true))) return rc;
         if (h->lat) {
             HIPCHECK(lattice_stage(h, 1, h->G, X, Y));
         } else {
             // the moments of fhat(t_n) are read by the update and overwritten by
             // the cell reduction that follows it on the same stream
-            LQStage a = lq_args(h, 1, h->G, X, Y);
-            HIPCHECK(launch_lq_stage(h->delta, h->p, a, h->stream, -1));
+            if ((rc = lq_stage(h, lq_args(h, 1, h->G, X, Y)))) return rc;
         }
-        if ((rc = record(h, KC_STAGE_C, false))) return rc;
+        if (whole && (rc = record(h, KC_STAGE_C, false))) return rc;
         h->cur = 1 - h->cur;
     }
     return DUGKS_OK;
@@ -1456,9 +1475,11 @@ int dugks_backward(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
         for (int t = len - 1; t >= 0; t--) {
             const void *Xt = t == 0 ? ck[i] : seg[t];
             if ((rc = stage_a_from(h, Xt))) return rc;
+            if ((rc = record(h, KC_ADJ_STEP, true))) return rc;
             HIPCHECK(adj_launch_prep(a, h->delta, p.rho0, Xt, h->G, fh_d, B, M, G_d, B2, M2, h->stream));
             HIPCHECK(adj_launch_step(a, lam[cur], lam[1 - cur], fh_d, B, M, G_d, B2, M2, lam_fbar, dtf, lamLs,
                                      lamB, lamF, dtau, h->stream));
+            if ((rc = record(h, KC_ADJ_STEP, false))) return rc;
             cur = 1 - cur;
         }
     }

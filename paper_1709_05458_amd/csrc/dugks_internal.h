@@ -143,7 +143,8 @@ struct StageIO {
 };
 
 // Kernel classes for event timing.
-enum KernelClass { KC_STAGE_A = 0, KC_STAGE_C = 1, KC_AUX = 2, KC_COUNT = 3 };
+enum KernelClass { KC_STAGE_A = 0, KC_STAGE_C = 1, KC_AUX = 2, KC_LQ_FACES = 3, KC_LQ_UPDATE = 4, KC_ADJ_STEP = 5,
+                   KC_COUNT = 6 };
 
 // Host launchers (defined in sweep.hip).  `lat`: 0 generic, 9 D2Q9, 37 D2Q37.
 // `delta`: FP32-delta storage (float) else FP64 storage (double).

@@ -20,7 +20,7 @@ T3S3, T2S3 = 0, 1   # time integrators (dugks_scheme)
 MEM_HOST, MEM_DEVICE = 0, 1
 ALLOW_MOMENT_DEFECT = 1
 FORCE_GENERIC = 2
-K_STAGE_A, K_STAGE_C, K_AUX = 0, 1, 2
+K_STAGE_A, K_STAGE_C, K_AUX, K_LQ_FACES, K_LQ_UPDATE, K_ADJ_STEP = 0, 1, 2, 3, 4, 5
 
 STATUS = {0: "DUGKS_OK", -1: "DUGKS_EINVAL", -2: "DUGKS_EUNSTABLE", -3: "DUGKS_EMOMENT",
           -4: "DUGKS_ENOMEM", -5: "DUGKS_EDEVICE", -6: "DUGKS_ENONFINITE", -7: "DUGKS_ENOTSUP"}

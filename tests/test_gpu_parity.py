@@ -305,3 +305,26 @@ def test_anysize_rejects_bounce_back():
     with pytest.raises(dugks.DugksError) as e:
         dugks.Solver(case)
     assert e.value.code == -7
+
+
+def test_any_size_profiling_times_faces_and_update_without_changing_results():
+    # while profiling, the any-size stages launch their four kernels with
+    # events between them: the same kernels in the same order on one stream
+    case = _mk("nc8_ds_tanh")
+    say("[gpu] any-size profiling nc8_ds_tanh FP32-delta")
+    runs = []
+    for prof in (False, True):
+        s = dugks.Solver(case, dugks.FP32_DELTA, allow_defect=True)
+        s.init_equilibrium(case.rho, case.ux, case.uy)
+        if prof:
+            s.prof_begin(64)
+        s.step(3)
+        if prof:
+            f_ms, f_n = s.prof_query(dugks.K_LQ_FACES)
+            u_ms, u_n = s.prof_query(dugks.K_LQ_UPDATE)
+            a_ms, a_n = s.prof_query(dugks.K_STAGE_A)
+            s.prof_end()
+            assert (f_n, u_n, a_n) == (6, 6, 0) and f_ms > 0 and u_ms > 0
+        runs.append(s.get_fhat())
+        s.close()
+    assert np.array_equal(runs[0], runs[1])
