@@ -29,19 +29,21 @@ UNIT = "G cell\u00b7velocity updates/s"
 # sources whose change invalidates stored hardware-counter traffic of the sweep kernels
 KERNEL_SOURCES = ["sweep_fast.hip", "sweep_common.h", "lattices.h",
                   "dugks_internal.h", "api.cpp"]
+# the same for the any-size kernels
+LQ_SOURCES = ["sweep_large.hip", "sweep_common.h", "dugks_internal.h", "api.cpp"]
 PROFILES = os.path.join(ROOT, "profiles")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=None) -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1709_05458_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def stored_traffic(summary: str, kernel_key: str):
+def stored_traffic(summary: str, kernel_key: str, sources=None):
     """HBM bytes per launch of one kernel from a stored counter summary
     (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the factor the
     same counter shows on a plain copy of known size), or None when the
@@ -55,7 +57,7 @@ def stored_traffic(summary: str, kernel_key: str):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("sources_sha256") != kernel_source_hash():
+    if kv.get("sources_sha256") != kernel_source_hash(sources):
         return None
     try:
         f_fetch = float(kv["fetch_scale"])
@@ -241,6 +243,8 @@ def run_rarefied(args):
                      "faces_frac": round(faces_gbs / HBM_PEAK_GBS, 4)}
         s.close()
     r = out["fp32"]
+    traffic = stored_traffic(f"any_size_rarefied_cavity{n}_nc{args.nc}_fp32delta_traffic.txt", "lq_faces",
+                             LQ_SOURCES)
     return {"metric": METRIC,
             "value": r["value"], "unit": UNIT, "n_gpus": 1,
             "steps": steps, "warmup": 2, "ms_per_step": r["ms_per_step"],
@@ -252,7 +256,8 @@ def run_rarefied(args):
             "fp64": out["fp64"],
             "roofline": {"bound": "hbm", "kernel": "lq_faces (any-size faces kernel, both stages)",
                          "achieved": r["faces_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": r["faces_frac"], "traffic": None, "bytes_per_launch": 3 * 4 * pairs,
+                         "frac": r["faces_frac"], "traffic": None if traffic is None else round(traffic),
+                         "bytes_per_launch": 3 * 4 * pairs,
                          "launch_ms": r["faces_ms"], "update_ms": r["update_ms"]},
             "cpu_baseline": None}
 

@@ -135,13 +135,17 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
 
     // (unused slots load the own cell again and write the spare element)
     S v[NS][Q];
+    S fv[STAGE == 1 ? Q : 1];   // stage C: fhat(t_n) of the own cell, loaded with the halo
     {
+        const size_t nf = (size_t)p.ncell_f;
         [&]<int... qs>(std::integer_sequence<int, qs...>) {
             (([&] {
 #pragma unroll
                  for (int s = 0; s < NS; s++)
                      v[s][qs] = *(const S *)((const char *)(X + (size_t)qs * n) +
                                              (unsigned)(sizeof(S) * (has[s] ? cell[s] : cell[0])));
+                 if constexpr (STAGE == 1)
+                     fv[qs] = *(const S *)((const char *)(F + (size_t)qs * nf) + (unsigned)(sizeof(S) * cell[0]));
              }()),
              ...);
         }(Seq{});
@@ -264,11 +268,10 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
         }
         const S sf = (S)a_f, sg = (S)a_G;
         double b0 = 0, bx = 0, by = 0;
-        const size_t nf = (size_t)p.ncell_f;
         [&]<int... qs>(std::integer_sequence<int, qs...>) {
             (([&] {
                  constexpr int EX = Lat::ex(qs), EY = Lat::ey(qs), SH = Lat::shell(qs);
-                 const S fq = *(const S *)((const char *)(F + (size_t)qs * nf) + (unsigned)(sizeof(S) * cell[0]));
+                 const S fq = fv[STAGE == 1 ? qs : 0];
                  const double d = (double)fq;
                  if (DELTA) {
                      b0 = __builtin_fma(p.wtab[SH][1], d, b0);
@@ -280,6 +283,9 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
                      if (EY) by = __builtin_fma((double)EY, d, by);
                  }
                  R0[qs] = fmaS(sf, fq, sg * v[0][qs]);
+                 // formed here, before the barrier: the loads of fhat then
+                 // overlap the halo loads instead of waiting after the fill
+                 asm volatile("" : "+v"(R0[qs]));
              }()),
              ...);
         }(Seq{});
