@@ -104,12 +104,17 @@ struct EPolyS {
         if (EX) ev = fmaS((S)(EX * EX), c2xx, ev);
         if (EX && EY) ev = fmaS((S)(EX * EY), c2xy, ev);
         if (EY) ev = fmaS((S)(EY * EY), c2yy, ev);
-        S od;
-        if (EX && EY) od = fmaS((S)EY, c1y, (S)EX * c1x);
-        else if (EX) od = (S)EX * c1x;
-        else od = (S)EY * c1y;
-        vp = ev + od;
-        vm = ev - od;
+        if (EX && EY) {
+            const S od = fmaS((S)EY, c1y, (S)EX * c1x);
+            vp = ev + od;
+            vm = ev - od;
+        } else if (EX) {
+            vp = fmaS((S)EX, c1x, ev);
+            vm = fmaS((S)-EX, c1x, ev);
+        } else {
+            vp = fmaS((S)EY, c1y, ev);
+            vm = fmaS((S)-EY, c1y, ev);
+        }
     }
 };
 
@@ -152,10 +157,11 @@ __device__ __forceinline__ void phys_moments(const SweepParams &p, bool delta, d
                                              double &mx, double &my)
 {
     if (delta) {
-        drho = p.rho0 * p.M0m1 + a0;
+        // (fused multiply-adds written out: the same rounding in every kernel)
+        drho = __builtin_fma(p.rho0, p.M0m1, a0);
         rho = p.rho0 + drho;
-        mx = p.rho0 * p.M1x + p.clat * ax;
-        my = p.rho0 * p.M1y + p.clat * ay;
+        mx = __builtin_fma(p.clat, ax, p.rho0 * p.M1x);
+        my = __builtin_fma(p.clat, ay, p.rho0 * p.M1y);
     } else {
         rho = a0;
         drho = a0;

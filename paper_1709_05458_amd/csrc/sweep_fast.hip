@@ -17,15 +17,17 @@
 //    into one cubic polynomial in the lattice vector before the last pass;
 //  * the linear part of the micro-flux is kept as one register per velocity,
 //    scaled by per-thread multiples of 1/dx, 1/dy chosen at compile time.
+// Every fused multiply-add of this file, and of the inline helpers it takes
+// from the headers below, is written out; no other contraction, so that the
+// single-instance and batched kernels round identically (a contractible
+// multiply and add may be fused in one kernel and not in the other).
+#pragma clang fp contract(off)
+
 #include "dugks_internal.h"
 #include "lattices.h"
 #include "sweep_common.h"
 
 #include <utility>
-
-// Every fused multiply-add of this file is written out; no other contraction,
-// so that the single-instance and batched kernels round identically.
-#pragma clang fp contract(off)
 
 namespace dk {
 
