@@ -101,9 +101,13 @@ __device__ __forceinline__ double face_bar(const AdjArgs &a, const double *Bs, c
 // micro-flux at cell c: scaleL * lamsrc(c, q).
 // Outputs lam_fbar [axis][q][cell] and the tau sensitivity of the face.
 // ---------------------------------------------------------------------------
-__global__ void adj_face(const AdjArgs a, int stage, const double *__restrict__ Bs, const double *__restrict__ lamsrc,
+template <int QC>
+__global__ void __launch_bounds__(256) adj_face(const AdjArgs a, int stage, const double *__restrict__ Bs, const double *__restrict__ lamsrc,
                          double scaleL, double *__restrict__ lam_fbar, double *__restrict__ dtau_face)
 {
+    // QC > 0: the velocity count at compile time; face values and flux
+    // adjoints stay in registers and each output is written once
+    const int nq = QC > 0 ? QC : a.nq;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= 2 * a.n) return;
     const int axis = t >= a.n;
@@ -116,10 +120,14 @@ __global__ void adj_face(const AdjArgs a, int stage, const double *__restrict__ 
     const double al = 2.0 * tb / (2.0 * tb + h), be = h / (2.0 * tb + h);
     const double dal = 2.0 * h / ((2.0 * tb + h) * (2.0 * tb + h));   // d alpha / d tau_b
     const double inv = axis ? a.idy : a.idx;
+    constexpr int NR = QC > 0 ? QC : 1;
+    double vq[NR], lq[NR];
     // pass 1: interface moments
     double r = 0, mx = 0, my = 0;
-    for (int q = 0; q < a.nq; q++) {
+#pragma unroll
+    for (int q = 0; q < nq; q++) {
         const double v = face_bar(a, Bs, cw, axis, i, j, q);
+        if (QC > 0) vq[QC > 0 ? q : 0] = v;
         r += v;
         mx += a.xi[q] * v;
         my += a.eta[q] * v;
@@ -127,7 +135,8 @@ __global__ void adj_face(const AdjArgs a, int stage, const double *__restrict__ 
     const double ux = mx / r, uy = my / r;
     // pass 2: adjoint of the recovery f = al fbar + be E(mom fbar) and of D
     double gR = 0, gX = 0, gY = 0, dt_b = 0;
-    for (int q = 0; q < a.nq; q++) {
+#pragma unroll
+    for (int q = 0; q < nq; q++) {
         const double xn = axis ? a.eta[q] : a.xi[q];
         const double lf = xn * inv * scaleL * (lamsrc[q * a.n + c] - lamsrc[q * a.n + cl]);
         double er, ex, ey;
@@ -135,12 +144,18 @@ __global__ void adj_face(const AdjArgs a, int stage, const double *__restrict__ 
         gR = __builtin_fma(be * lf, er, gR);
         gX = __builtin_fma(be * lf, ex, gX);
         gY = __builtin_fma(be * lf, ey, gY);
-        const double v = face_bar(a, Bs, cw, axis, i, j, q);
+        const double v = QC > 0 ? vq[QC > 0 ? q : 0] : face_bar(a, Bs, cw, axis, i, j, q);
         dt_b = __builtin_fma(lf * dal, v - eq_val(a, q, r, ux, uy), dt_b);
-        lam_fbar[((long long)axis * a.nq + q) * a.n + c] = al * lf;
+        if (QC > 0)
+            lq[QC > 0 ? q : 0] = lf;
+        else
+            lam_fbar[((long long)axis * nq + q) * a.n + c] = al * lf;
     }
-    for (int q = 0; q < a.nq; q++)
-        lam_fbar[((long long)axis * a.nq + q) * a.n + c] += gR + gX * a.xi[q] + gY * a.eta[q];
+#pragma unroll
+    for (int q = 0; q < nq; q++) {
+        const double base = QC > 0 ? al * lq[QC > 0 ? q : 0] : lam_fbar[((long long)axis * nq + q) * a.n + c];
+        lam_fbar[((long long)axis * nq + q) * a.n + c] = base + (gR + gX * a.xi[q] + gY * a.eta[q]);
+    }
     dtau_face[t] = dt_b;
 }
 
@@ -312,18 +327,30 @@ hipError_t adj_launch_prep(const AdjArgs &a, bool delta, double rho0, const void
     return hipGetLastError();
 }
 
+// face adjoint with the velocity count fixed at compile time for D2Q9 (at 37
+// velocities the unrolled kernel no longer fits the register file)
+static void launch_adj_face(const AdjArgs &a, int stage, const double *Bs, const double *lamsrc, double scaleL,
+                            double *lam_fbar, double *dtau_face, hipStream_t s)
+{
+    if (a.nq == 9)
+        hipLaunchKernelGGL(adj_face<9>, g1(2 * a.n), dim3(256), 0, s, a, stage, Bs, lamsrc, scaleL, lam_fbar,
+                           dtau_face);
+    else
+        hipLaunchKernelGGL(adj_face<0>, g1(2 * a.n), dim3(256), 0, s, a, stage, Bs, lamsrc, scaleL, lam_fbar,
+                           dtau_face);
+}
+
 hipError_t adj_launch_step(const AdjArgs &a, const double *lam_out, double *lam_in, const double *fh_d,
                            const double *B, const double *M, const double *G_d, const double *B2,
                            const double *M2, double *lam_fbar, double *dtau_face, double *lamLs, double *lamB,
                            double *lamF, double *dtau, hipStream_t s)
 {
     // stage C (reverse of steps (3)-(4))
-    hipLaunchKernelGGL(adj_face, g1(2 * a.n), dim3(256), 0, s, a, 1, B2, lam_out, 4.0 * a.dt / 7.0, lam_fbar,
-                       dtau_face);
+    launch_adj_face(a, 1, B2, lam_out, 4.0 * a.dt / 7.0, lam_fbar, dtau_face, s);
     hipLaunchKernelGGL(adj_cellC, g1(a.n), dim3(256), 0, s, a, lam_out, lam_fbar, dtau_face, G_d, M2, lamLs,
                        lamB, lamF, dtau);
     // stage A (reverse of steps (1)-(2))
-    hipLaunchKernelGGL(adj_face, g1(2 * a.n), dim3(256), 0, s, a, 0, B, lamLs, 1.0, lam_fbar, dtau_face);
+    launch_adj_face(a, 0, B, lamLs, 1.0, lam_fbar, dtau_face, s);
     hipLaunchKernelGGL(adj_cellA, g1(a.n), dim3(256), 0, s, a, lam_fbar, dtau_face, fh_d, M, lamB, lamF, lam_in,
                        dtau);
     return hipGetLastError();
