@@ -834,7 +834,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 lq_faces(const SweepParams p, const LQStage a)
 {
     const int ntile = lq_ntile(p);
-    lq_faces_body<S, DELTA>(p, a, blockIdx.x % ntile, blockIdx.x / ntile);
+    // XCD-aware order: consecutive blocks go to different XCDs, so each XCD
+    // takes a contiguous band of (tile, chunk) indices; neighbouring tiles of
+    // one chunk then share their ring rows and face lines in one L2
+    const int nb = ntile * p.lq_nchunk, b = blockIdx.x, nx8 = p.nxcd;
+    const int per = nb / nx8, rem = nb % nx8;
+    const int x = b % nx8, slot = b / nx8;
+    const int t = x * per + (x < rem ? x : rem) + slot;
+    lq_faces_body<S, DELTA>(p, a, t % ntile, t / ntile);
 }
 
 template <class S, bool DELTA>
