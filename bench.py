@@ -43,6 +43,12 @@ def kernel_source_hash(sources=None) -> str:
     return h.hexdigest()[:16]
 
 
+def traffic_summary_name(n: int, lattice_name: str) -> str:
+    """File under profiles/ holding the stage kernels' counter traffic of the
+    Taylor-Green workload with n x n cells and the named velocity set."""
+    return f"sweep_stages_tgv{n}_{lattice_name.lower()}_fp32delta_traffic.txt"
+
+
 def stored_traffic(summary: str, kernel_key: str, sources=None):
     """HBM bytes per launch of one kernel from a stored counter summary
     (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by the factor the
@@ -377,8 +383,7 @@ def main():
     bytes_dom = per_pair * s * pairs
     dom_ms = r32["stage_c_ms"] if dom == "C" else r32["stage_a_ms"]
     achieved = bytes_dom / (dom_ms * 1e-3) / 1e9
-    wl = f"tgv{args.n}_{case.vs.name}_fp32delta"
-    traffic = stored_traffic(f"sweep_stages_{wl}_traffic.txt", f"stage_{dom.lower()}")
+    traffic = stored_traffic(traffic_summary_name(args.n, case.vs.name), f"stage_{dom.lower()}")
     out = {
         "metric": METRIC,
         "value": round(gcups, 3),

@@ -80,3 +80,12 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(dugks, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(ImportError):
         dugks.lib()
+
+
+def test_bench_finds_the_stored_traffic_summary_of_its_default_workload():
+    # the name is built from the velocity set's name ("D2Q37"); the file on
+    # disk is lower case, and a case-sensitive file system must still find it
+    import bench
+    from paper_1709_05458_amd import cases as C
+    name = bench.traffic_summary_name(2048, C.d2q37(1.0 / 3.0).name)
+    assert os.path.exists(os.path.join(bench.PROFILES, name)), name
