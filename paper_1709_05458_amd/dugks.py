@@ -258,6 +258,27 @@ class Solver:
     def sync(self):
         check(lib().dugks_sync(self.h), "dugks_sync")
 
+    def run_until_steady(self, tol: float = 1e-6, every: int = 1000, max_steps: int = 1_000_000):
+        """Step until the paper's steady-state criterion holds (cavity section):
+        sqrt(sum |u^(n+every) - u^(n)|^2) / sqrt(sum |u^(n+every)|^2) <= tol,
+        checked every `every` steps.  Returns (steps taken, last residual); the
+        residual is None if fewer than two checks ran.  Raises DugksError on a
+        non-finite state."""
+        _, ux, uy = self.moments()
+        done, res = 0, None
+        while done < max_steps:
+            n = min(every, max_steps - done)
+            self.step(n)
+            done += n
+            self.sync()
+            _, vx, vy = self.moments()
+            den = float(np.sqrt((vx * vx + vy * vy).sum()))
+            res = float(np.sqrt(((vx - ux) ** 2 + (vy - uy) ** 2).sum())) / den if den > 0 else 0.0
+            ux, uy = vx, vy
+            if n == every and res <= tol:
+                break
+        return done, res
+
     def set_tau(self, tau):
         p, mem, keep = _ptr_mem(tau)
         check(lib().dugks_set_tau(self.h, p, mem), "dugks_set_tau")
@@ -414,6 +435,27 @@ class BatchSolver:
 
     def sync(self):
         check(lib().dugks_sync(self.h), "dugks_sync")
+
+    def run_until_steady(self, tol: float = 1e-6, every: int = 1000, max_steps: int = 1_000_000):
+        """Step until the paper's steady-state criterion holds (cavity section):
+        sqrt(sum |u^(n+every) - u^(n)|^2) / sqrt(sum |u^(n+every)|^2) <= tol,
+        checked every `every` steps.  Returns (steps taken, last residual); the
+        residual is None if fewer than two checks ran.  Raises DugksError on a
+        non-finite state."""
+        _, ux, uy = self.moments()
+        done, res = 0, None
+        while done < max_steps:
+            n = min(every, max_steps - done)
+            self.step(n)
+            done += n
+            self.sync()
+            _, vx, vy = self.moments()
+            den = float(np.sqrt((vx * vx + vy * vy).sum()))
+            res = float(np.sqrt(((vx - ux) ** 2 + (vy - uy) ** 2).sum())) / den if den > 0 else 0.0
+            ux, uy = vx, vy
+            if n == every and res <= tol:
+                break
+        return done, res
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(256)
