@@ -28,9 +28,9 @@ METRIC = "G cell\u00b7velocity updates/s per DUGKS step + %HBM peak, FP32-\u03b4
 UNIT = "G cell\u00b7velocity updates/s"
 # sources whose change invalidates stored hardware-counter traffic of the sweep kernels
 KERNEL_SOURCES = ["sweep_fast.hip", "sweep_common.h", "lattices.h",
-                  "dugks_internal.h", "api.cpp"]
+                  "dugks_internal.h", "api.cpp", "../build.py"]   # (build flags shape the code too)
 # the same for the any-size kernels
-LQ_SOURCES = ["sweep_large.hip", "sweep_common.h", "dugks_internal.h", "api.cpp"]
+LQ_SOURCES = ["sweep_large.hip", "sweep_common.h", "dugks_internal.h", "api.cpp", "../build.py"]
 PROFILES = os.path.join(ROOT, "profiles")
 
 

@@ -17,8 +17,11 @@ FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # The lattice kernels read their LDS windows at compile-time offsets from one
 # base; LLVM's IR load/store vectorizer would pair neighbouring reads behind a
-# fresh base register each (one extra VALU add per pair).
-EXTRA = {"sweep_fast.hip": ["-mllvm", "-amdgpu-load-store-vectorizer=false"]}
+# fresh base register each (one extra VALU add per pair).  Their occupancy is
+# fixed by LDS (two blocks per CU), so the scheduler is told to favour
+# instruction-level parallelism over registers (3% faster on 2048^2 D2Q37).
+EXTRA = {"sweep_fast.hip": ["-mllvm", "-amdgpu-load-store-vectorizer=false",
+                            "-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
 
 
 def hipcc() -> str:
