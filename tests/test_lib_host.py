@@ -89,3 +89,15 @@ def test_bench_finds_the_stored_traffic_summary_of_its_default_workload():
     from paper_1709_05458_amd import cases as C
     name = bench.traffic_summary_name(2048, C.d2q37(1.0 / 3.0).name)
     assert os.path.exists(os.path.join(bench.PROFILES, name)), name
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # this build measures one GPU; asking for more must fail with a message,
+    # before anything touches a device
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
