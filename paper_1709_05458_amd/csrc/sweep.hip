@@ -442,7 +442,10 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
                                            cls * (S)Lat::ex(qs), cls * (S)Lat::ey(qs)), ...);
         }(Seq{});
     } else {
-        [&]<int... qs>(std::integer_sequence<int, qs...>) {
+        // always_inline: left out of line (it is large for Q = 37), this fold
+        // makes the parameters, the thread state and the closure addressable,
+        // and every read of them then goes through scratch memory
+        [&]<int... qs>(std::integer_sequence<int, qs...>) __attribute__((always_inline)) {
             (faces_general<Lat, S, DELTA, qs>(t, p, lds, plane, HX, lx + 2, ly + 2, i, j, h, o_rho,
                                               W[qs], WM, cls * (S)Lat::ex(qs), cls * (S)Lat::ey(qs)),
              ...);
@@ -534,9 +537,11 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
 }
 
 // Single instance: tiles from the block index (XCD-aware order); each kind of
-// tile is handled by its own instantiation.
-template <class Lat, class S, bool DELTA, int STAGE, bool GENERAL>
-__global__ void __launch_bounds__(512)
+// tile is handled by its own instantiation.  MAXT bounds the block: tiles of up
+// to 256 cells run one wave per SIMD, so the compiler may use the whole
+// 512-entry register file (arch VGPRs + AGPRs) instead of spilling to scratch.
+template <class Lat, class S, bool DELTA, int STAGE, bool GENERAL, int MAXT>
+__global__ void __launch_bounds__(MAXT)
 sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
             const S *__restrict__ F, S *__restrict__ out, const S *__restrict__ coef)
 {
@@ -574,22 +579,37 @@ static hipError_t launch_t(const SweepParams &p, double h, const void *X, const 
     // general kind exist unless the domain is uniform and fully periodic
     const bool any_fast = p.uniform && (parts & 1);
     const bool any_general = !(p.uniform && p.perx && p.pery) && (parts & 2);
-    if (any_fast)
-        hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, false>), grid, block, smem, s, p, h,
-                           (const S *)X, (const S *)F, (S *)out, (const S *)coef);
-    if (any_general)
-        hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, true>), grid, block, smem, s, p, h,
-                           (const S *)X, (const S *)F, (S *)out, (const S *)coef);
+    const bool small = p.tile_x * p.tile_y <= 256;
+    if (any_fast) {
+        if (small)
+            hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, false, 256>), grid, block, smem, s, p, h,
+                               (const S *)X, (const S *)F, (S *)out, (const S *)coef);
+        else
+            hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, false, 512>), grid, block, smem, s, p, h,
+                               (const S *)X, (const S *)F, (S *)out, (const S *)coef);
+    }
+    if (any_general) {
+        if (small)
+            hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, true, 256>), grid, block, smem, s, p, h,
+                               (const S *)X, (const S *)F, (S *)out, (const S *)coef);
+        else
+            hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, true, 512>), grid, block, smem, s, p, h,
+                               (const S *)X, (const S *)F, (S *)out, (const S *)coef);
+    }
     return hipGetLastError();
 }
 
 template <class Lat, class S, bool DELTA>
 static hipError_t smem_t(size_t bytes)
 {
-    const void *fns[8] = {(const void *)sweep_small<Lat, S, DELTA, 0, false>,
-                          (const void *)sweep_small<Lat, S, DELTA, 1, false>,
-                          (const void *)sweep_small<Lat, S, DELTA, 0, true>,
-                          (const void *)sweep_small<Lat, S, DELTA, 1, true>,
+    const void *fns[12] = {(const void *)sweep_small<Lat, S, DELTA, 0, false, 256>,
+                          (const void *)sweep_small<Lat, S, DELTA, 1, false, 256>,
+                          (const void *)sweep_small<Lat, S, DELTA, 0, true, 256>,
+                          (const void *)sweep_small<Lat, S, DELTA, 1, true, 256>,
+                          (const void *)sweep_small<Lat, S, DELTA, 0, false, 512>,
+                          (const void *)sweep_small<Lat, S, DELTA, 1, false, 512>,
+                          (const void *)sweep_small<Lat, S, DELTA, 0, true, 512>,
+                          (const void *)sweep_small<Lat, S, DELTA, 1, true, 512>,
                           (const void *)sweep_small_batched<Lat, S, DELTA, 0, false>,
                           (const void *)sweep_small_batched<Lat, S, DELTA, 1, false>,
                           (const void *)sweep_small_batched<Lat, S, DELTA, 0, true>,
