@@ -88,10 +88,11 @@ def parse():
     ap.add_argument("--scheme", default="t3s3", choices=["t3s3", "t2s3"],
                     help="time integrator of the Taylor-Green workload (t2s3: the paper's second-order "
                          "comparison scheme, one sweep per step)")
-    ap.add_argument("--workload", default="tgv", choices=["tgv", "batched", "rarefied", "adjoint"],
+    ap.add_argument("--workload", default="tgv", choices=["tgv", "batched", "rarefied", "adjoint", "cavity"],
                     help="tgv: Taylor-Green (headline); batched: 64 uneven cavities in one graph "
                          "launch per step; rarefied: Newton-Cotes cavity on stretched cells; adjoint: "
-                         "gradient of 500 Taylor-Green 256^2 D2Q9 steps (dugks_backward)")
+                         "gradient of 500 Taylor-Green 256^2 D2Q9 steps (dugks_backward); cavity: "
+                         "lid-driven cavity at Re 1000 with bounce-back walls (--n, --lattice)")
     ap.add_argument("--nc", type=int, default=101, help="Newton-Cotes points per axis (rarefied)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
@@ -319,6 +320,50 @@ def run_adjoint(args):
             "cpu_baseline": None}
 
 
+def run_cavity(args):
+    """Lid-driven cavity (the paper's wall-bounded flow): [0,1]^2, bounce-back walls,
+    lid Ma 0.1 against sqrt(3 RT), Re 1000, n x n cells, D2Q9 or D2Q37,
+    FP32-delta with FP64 beside it.  Interior tiles run the compile-time-shape
+    kernels, tiles touching a wall the general ones."""
+    import torch
+    from paper_1709_05458_amd import cases as C, dugks
+    vs = C.d2q37(1.0 / 3.0) if args.lattice == "d2q37" else C.d2q9(1.0 / 3.0)
+    case = C.cavity_case(args.n, vs, re=1000.0)
+    pairs = args.n * args.n * vs.nq
+    out = {}
+    for prec, name, steps in ((dugks.FP32_DELTA, "fp32", args.steps), (dugks.FP64, "fp64", max(10, args.steps // 4))):
+        s = dugks.Solver(case, prec)
+        s.init_equilibrium(case.rho, case.ux, case.uy)
+        m0 = float(s.moments()[0].sum())
+        s.step(args.warmup)
+        s.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        s.sync()   # raises on a non-finite state
+        r, ux, uy = s.moments()
+        out[name] = {"value": round(pairs / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 5),
+                     "variant": s.describe(), "steps": steps,
+                     "mass_rel_drift": abs(float(r.sum()) - m0) / m0,
+                     "u_max_over_lid": float(np.abs(ux).max() / case.meta["U"])}
+        s.close()
+    r32 = out["fp32"]
+    return {"metric": METRIC,
+            "value": r32["value"], "unit": UNIT, "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": r32["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"lid-driven cavity {args.n}x{args.n}, {vs.name}, Re 1000, lid Ma 0.1, "
+                                   "bounce-back walls, FP32-delta storage",
+                       "pairs": pairs, "variant": r32["variant"]},
+            "fp64": out["fp64"], "checks": {k: {"mass_rel_drift": out[k]["mass_rel_drift"],
+                                                "u_max_over_lid": out[k]["u_max_over_lid"]} for k in out},
+            "roofline": None, "cpu_baseline": None}
+
+
 def cpu_baseline(lattice):
     """The oracle as it stands on the host cores, on a bounded sample of the
     same workload (Taylor-Green, same velocity set, 256 x 256, a few steps)."""
@@ -359,6 +404,9 @@ def main():
         return
     if args.workload == "adjoint":
         print(json.dumps(run_adjoint(args)))
+        return
+    if args.workload == "cavity":
+        print(json.dumps(run_cavity(args)))
         return
     tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
     case = make_case(args.n, args.lattice)
