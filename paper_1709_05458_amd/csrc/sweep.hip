@@ -536,6 +536,37 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
     }(Seq{});
 }
 
+// On a uniform grid the fast-kind tiles form the rectangle of tile columns
+// [cx0, cx1) by tile rows [ry0, ry1); the general kind is the ring around it
+// (the tiles within two cells of a wall).  With on = 1 a general launch has
+// one block per ring tile: the rows below the rectangle, then the side tiles
+// of its rows, then the rows above, ng tiles in all.
+struct Ring {
+    int on, gx, cx0, cx1, ry0, ry1, ng;
+};
+
+__device__ __forceinline__ void ring_tile(const Ring &r, int nxcd, int &tx, int &ty)
+{
+    // XCD-aware: the blocks of one XCD take a contiguous run of ring tiles
+    const int per = r.ng / nxcd, rem = r.ng % nxcd;
+    const int x = blockIdx.x % nxcd, slot = blockIdx.x / nxcd;
+    const int b = x * per + (x < rem ? x : rem) + slot;
+    const int fx = r.cx1 - r.cx0, side = r.gx - fx;
+    const int nb = r.ry0 * r.gx, nm = (r.ry1 - r.ry0) * side;
+    if (b < nb) {
+        ty = b / r.gx;
+        tx = b % r.gx;
+    } else if (b - nb < nm) {
+        const int k = b - nb, c = k % side;
+        ty = r.ry0 + k / side;
+        tx = c < r.cx0 ? c : c + fx;
+    } else {
+        const int k = b - nb - nm;
+        ty = r.ry1 + k / r.gx;
+        tx = k % r.gx;
+    }
+}
+
 // Single instance: tiles from the block index (XCD-aware order); each kind of
 // tile is handled by its own instantiation.  MAXT bounds the block: tiles of up
 // to 256 cells run one wave per SIMD, so the compiler may use the whole
@@ -543,12 +574,41 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
 template <class Lat, class S, bool DELTA, int STAGE, bool GENERAL, int MAXT>
 __global__ void __launch_bounds__(MAXT)
 sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
-            const S *__restrict__ F, S *__restrict__ out, const S *__restrict__ coef)
+            const S *__restrict__ F, S *__restrict__ out, const S *__restrict__ coef, const Ring r)
 {
     int tx, ty;
-    tile_of_block(p, tx, ty);
+    if (GENERAL && r.on) ring_tile(r, p.nxcd, tx, ty);
+    else tile_of_block(p, tx, ty);
     if (tile_is_fast(p, tx * p.tile_x, ty * p.tile_y, p.tile_x, p.tile_y) == GENERAL) return;
     sweep_small_body<Lat, S, DELTA, STAGE, GENERAL>(p, h, X, F, out, coef, tx, ty);
+}
+
+// The ring of general tiles of a uniform grid (Ring::on = 0 where every tile is
+// general, or none is).  Mirrors tile_is_fast per tile column and tile row.
+static Ring ring_of(const SweepParams &p)
+{
+    Ring r{0, 0, 0, 0, 0, 0, 0};
+    const int gx = (p.nx + p.tile_x - 1) / p.tile_x, gy = (p.ny + p.tile_y - 1) / p.tile_y;
+    if (!p.uniform) return r;
+    auto range = [](bool per, int g, int t, int n, int &a, int &b) {
+        a = g;
+        b = 0;
+        for (int k = 0; k < g; k++) {
+            const int i0 = k * t;
+            if (per || (i0 >= 2 && i0 + t <= n - 2)) {
+                a = k < a ? k : a;
+                b = k + 1;
+            }
+        }
+        if (b <= a) a = b = 0;
+    };
+    int cx0, cx1, ry0, ry1;
+    range(p.perx != 0, gx, p.tile_x, p.nx, cx0, cx1);
+    range(p.pery != 0, gy, p.tile_y, p.ny, ry0, ry1);
+    const long long nfast = (long long)(cx1 - cx0) * (ry1 - ry0);
+    if (nfast == 0) return r;
+    r = Ring{1, gx, cx0, cx1, ry0, ry1, (int)((long long)gx * gy - nfast)};
+    return r;
 }
 
 // Many instances in one launch: block b works on work[b] = (instance, tile x,
@@ -580,21 +640,26 @@ static hipError_t launch_t(const SweepParams &p, double h, const void *X, const 
     const bool any_fast = p.uniform && (parts & 1);
     const bool any_general = !(p.uniform && p.perx && p.pery) && (parts & 2);
     const bool small = p.tile_x * p.tile_y <= 256;
+    const Ring none{0, 0, 0, 0, 0, 0, 0};
     if (any_fast) {
         if (small)
             hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, false, 256>), grid, block, smem, s, p, h,
-                               (const S *)X, (const S *)F, (S *)out, (const S *)coef);
+                               (const S *)X, (const S *)F, (S *)out, (const S *)coef, none);
         else
             hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, false, 512>), grid, block, smem, s, p, h,
-                               (const S *)X, (const S *)F, (S *)out, (const S *)coef);
+                               (const S *)X, (const S *)F, (S *)out, (const S *)coef, none);
     }
     if (any_general) {
+        // a uniform grid with walls: one block per tile of the ring only
+        const Ring r = ring_of(p);
+        const dim3 ggrid(r.on ? (unsigned)r.ng : grid.x);
+        if (r.on && r.ng == 0) return hipGetLastError();
         if (small)
-            hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, true, 256>), grid, block, smem, s, p, h,
-                               (const S *)X, (const S *)F, (S *)out, (const S *)coef);
+            hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, true, 256>), ggrid, block, smem, s, p, h,
+                               (const S *)X, (const S *)F, (S *)out, (const S *)coef, r);
         else
-            hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, true, 512>), grid, block, smem, s, p, h,
-                               (const S *)X, (const S *)F, (S *)out, (const S *)coef);
+            hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, true, 512>), ggrid, block, smem, s, p, h,
+                               (const S *)X, (const S *)F, (S *)out, (const S *)coef, r);
     }
     return hipGetLastError();
 }
