@@ -92,7 +92,8 @@ def parse():
                     help="tgv: Taylor-Green (headline); batched: 64 uneven cavities in one graph "
                          "launch per step; rarefied: Newton-Cotes cavity on stretched cells; adjoint: "
                          "gradient of 500 Taylor-Green 256^2 D2Q9 steps (dugks_backward); cavity: "
-                         "lid-driven cavity at Re 1000 with bounce-back walls (--n, --lattice)")
+                         "lid-driven cavity at Re 1000 with bounce-back walls (--n, --lattice, --tile; 16x16 "
+                         "by default)")
     ap.add_argument("--nc", type=int, default=101, help="Newton-Cotes points per axis (rarefied)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
@@ -330,9 +331,13 @@ def run_cavity(args):
     vs = C.d2q37(1.0 / 3.0) if args.lattice == "d2q37" else C.d2q9(1.0 / 3.0)
     case = C.cavity_case(args.n, vs, re=1000.0)
     pairs = args.n * args.n * vs.nq
+    # 16 x 16 tiles: the ring of wall tiles that the general kernel takes is
+    # 508 tiles (two rounds of blocks at one block per CU) against 636 for the
+    # 32 x 8 default, which is best on periodic grids
+    tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else (16, 16)
     out = {}
     for prec, name, steps in ((dugks.FP32_DELTA, "fp32", args.steps), (dugks.FP64, "fp64", max(10, args.steps // 4))):
-        s = dugks.Solver(case, prec)
+        s = dugks.Solver(case, prec, tile=tile)
         s.init_equilibrium(case.rho, case.ux, case.uy)
         m0 = float(s.moments()[0].sum())
         s.step(args.warmup)
