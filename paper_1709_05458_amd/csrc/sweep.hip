@@ -568,9 +568,10 @@ __device__ __forceinline__ void ring_tile(const Ring &r, int nxcd, int &tx, int 
 }
 
 // Single instance: tiles from the block index (XCD-aware order); each kind of
-// tile is handled by its own instantiation.  MAXT bounds the block: tiles of up
-// to 256 cells run one wave per SIMD, so the compiler may use the whole
-// 512-entry register file (arch VGPRs + AGPRs) instead of spilling to scratch.
+// tile is handled by its own instantiation.  MAXT bounds the block: at 256 (a
+// tile of up to 256 cells, one wave per SIMD) the compiler may use the whole
+// 512-entry register file (arch VGPRs + AGPRs) instead of spilling to scratch;
+// the launcher takes that bound where LDS admits only one block per CU.
 template <class Lat, class S, bool DELTA, int STAGE, bool GENERAL, int MAXT>
 __global__ void __launch_bounds__(MAXT)
 sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
@@ -654,7 +655,12 @@ static hipError_t launch_t(const SweepParams &p, double h, const void *X, const 
         const Ring r = ring_of(p);
         const dim3 ggrid(r.on ? (unsigned)r.ng : grid.x);
         if (r.on && r.ng == 0) return hipGetLastError();
-        if (small)
+        // two waves per SIMD pay only where two blocks fit in a CU's 160 KB of
+        // LDS (D2Q37 FP32-delta on a 16 x 16 tile: 508 ring tiles of 2048^2
+        // in one round of blocks instead of two, 15% faster per step despite
+        // the spills at that bound); otherwise one wave with every register
+        const bool two_blocks = 2 * smem <= 160u * 1024u;
+        if (small && !two_blocks)
             hipLaunchKernelGGL((sweep_small<Lat, S, DELTA, STAGE, true, 256>), ggrid, block, smem, s, p, h,
                                (const S *)X, (const S *)F, (S *)out, (const S *)coef, r);
         else
