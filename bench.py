@@ -342,20 +342,42 @@ def run_cavity(args):
         m0 = float(s.moments()[0].sum())
         s.step(args.warmup)
         s.sync()
+        s.prof_begin(2 * steps + 8)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         s.step(steps)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / steps
+        a_ms, _ = s.prof_query(dugks.K_STAGE_A)
+        c_ms, _ = s.prof_query(dugks.K_STAGE_C)
+        s.prof_end()
         s.sync()   # raises on a non-finite state
         r, ux, uy = s.moments()
         out[name] = {"value": round(pairs / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 5),
                      "variant": s.describe(), "steps": steps,
                      "mass_rel_drift": abs(float(r.sum()) - m0) / m0,
-                     "u_max_over_lid": float(np.abs(ux).max() / case.meta["U"])}
+                     "u_max_over_lid": float(np.abs(ux).max() / case.meta["U"]),
+                     "stage_a_ms": a_ms, "stage_c_ms": c_ms}
         s.close()
     r32 = out["fp32"]
+    # dominant stage, timed as one record over its launches (the fast kernel
+    # on the interior tiles, the general one on the ring of wall tiles);
+    # algorithmic bytes as for the periodic flow: 3 stored elements per pair
+    # for stage C, 2 for stage A
+    dom = "C" if r32["stage_c_ms"] >= r32["stage_a_ms"] else "A"
+    dom_ms = r32["stage_c_ms"] if dom == "C" else r32["stage_a_ms"]
+    bytes_dom = (3 if dom == "C" else 2) * 4 * pairs
+    achieved = bytes_dom / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": f"stage {dom} (sweep_fast on interior tiles + sweep_small on the "
+                                          "wall ring, one record)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": bytes_dom, "launch_ms": round(dom_ms, 5),
+                "stage_a_ms": round(r32["stage_a_ms"], 5), "stage_c_ms": round(r32["stage_c_ms"], 5)}
+    for k in out:
+        out[k]["stage_a_ms"] = round(out[k]["stage_a_ms"], 5)
+        out[k]["stage_c_ms"] = round(out[k]["stage_c_ms"], 5)
     return {"metric": METRIC,
             "value": r32["value"], "unit": UNIT, "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": r32["ms_per_step"],
@@ -366,7 +388,7 @@ def run_cavity(args):
                        "pairs": pairs, "variant": r32["variant"]},
             "fp64": out["fp64"], "checks": {k: {"mass_rel_drift": out[k]["mass_rel_drift"],
                                                 "u_max_over_lid": out[k]["u_max_over_lid"]} for k in out},
-            "roofline": None, "cpu_baseline": None}
+            "roofline": roofline, "cpu_baseline": None}
 
 
 def cpu_baseline(lattice):
