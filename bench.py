@@ -159,7 +159,18 @@ def time_run(case, precision, steps, warmup, tile, scheme=0):
               "u_rel_l2_vs_analytic_decay": err}
     return {"ms_per_step": ms_total / steps, "stage_a_ms": a_ms, "stage_c_ms": c_ms,
             "launches": (a_n, c_n), "variant": desc, "u_max": float(max(np.abs(ux).max(), np.abs(uy).max())),
-            "mass": float(r.mean()), "checks": checks}
+            "mass": float(r.mean()), "checks": checks, "_u": (ux, uy)}
+
+
+def precision_gap(u32, u64):
+    """FP32-delta velocity field against the FP64 one after the same steps from
+    the same initial state: max |u32 - u64| / max |u64| and the relative L2
+    distance (both components)."""
+    d = max(float(np.abs(a - b).max()) for a, b in zip(u32, u64))
+    m = max(float(np.abs(b).max()) for b in u64)
+    l2 = math.sqrt(sum(float(((a - b) ** 2).sum()) for a, b in zip(u32, u64)) /
+                   sum(float((b ** 2).sum()) for b in u64))
+    return {"u_max_rel_diff": d / m, "u_rel_l2": l2}
 
 
 def run_batched(args):
@@ -336,7 +347,7 @@ def run_cavity(args):
     # 32 x 8 default, which is best on periodic grids
     tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else (16, 16)
     out = {}
-    for prec, name, steps in ((dugks.FP32_DELTA, "fp32", args.steps), (dugks.FP64, "fp64", max(10, args.steps // 4))):
+    for prec, name, steps in ((dugks.FP32_DELTA, "fp32", args.steps), (dugks.FP64, "fp64", args.steps)):
         s = dugks.Solver(case, prec, tile=tile)
         s.init_equilibrium(case.rho, case.ux, case.uy)
         m0 = float(s.moments()[0].sum())
@@ -358,8 +369,9 @@ def run_cavity(args):
                      "variant": s.describe(), "steps": steps,
                      "mass_rel_drift": abs(float(r.sum()) - m0) / m0,
                      "u_max_over_lid": float(np.abs(ux).max() / case.meta["U"]),
-                     "stage_a_ms": a_ms, "stage_c_ms": c_ms}
+                     "stage_a_ms": a_ms, "stage_c_ms": c_ms, "_u": (ux, uy)}
         s.close()
+    gap = precision_gap(out["fp32"].pop("_u"), out["fp64"].pop("_u"))
     r32 = out["fp32"]
     # dominant stage, timed as one record over its launches (the fast kernel
     # on the interior tiles, the general one on the ring of wall tiles);
@@ -386,8 +398,10 @@ def run_cavity(args):
             "config": {"workload": f"lid-driven cavity {args.n}x{args.n}, {vs.name}, Re 1000, lid Ma 0.1, "
                                    "bounce-back walls, FP32-delta storage",
                        "pairs": pairs, "variant": r32["variant"]},
-            "fp64": out["fp64"], "checks": {k: {"mass_rel_drift": out[k]["mass_rel_drift"],
-                                                "u_max_over_lid": out[k]["u_max_over_lid"]} for k in out},
+            "fp64": out["fp64"],
+            "checks": dict({k: {"mass_rel_drift": out[k]["mass_rel_drift"],
+                                "u_max_over_lid": out[k]["u_max_over_lid"]} for k in out},
+                           fp32_vs_fp64=dict(gap, steps_total=args.warmup + args.steps)),
             "roofline": roofline, "cpu_baseline": None}
 
 
@@ -442,10 +456,13 @@ def main():
     print(f"# bench: TGV {args.n}^2 {case.vs.name} FP32-delta, {args.steps} steps", file=sys.stderr, flush=True)
     scheme = dugks.T2S3 if args.scheme == "t2s3" else dugks.T3S3
     r32 = time_run(case, dugks.FP32_DELTA, args.steps, args.warmup, tile, scheme)
+    u32 = r32.pop("_u")
     print(f"# fp32-delta: {r32}", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_fp64:
-        r64 = time_run(case, dugks.FP64, max(10, args.steps // 4), args.warmup, tile, scheme)
+        # the same steps from the same initial state, so that the two fields compare
+        r64 = time_run(case, dugks.FP64, args.steps, args.warmup, tile, scheme)
+        u64 = r64.pop("_u")
         print(f"# fp64: {r64}", file=sys.stderr, flush=True)
     gcups = pairs / (r32["ms_per_step"] * 1e-3) / 1e9
     # dominant kernel (the longer of the two stage kernels).  Algorithmic
@@ -483,7 +500,9 @@ def main():
                      "bytes_per_launch": bytes_dom, "launch_ms": round(dom_ms, 5),
                      "stage_a_ms": round(r32["stage_a_ms"], 5), "stage_c_ms": round(r32["stage_c_ms"], 5)},
     }
-    out["checks"] = {"fp32_delta": r32["checks"], "fp64": r64["checks"] if r64 else None}
+    out["checks"] = {"fp32_delta": r32["checks"], "fp64": r64["checks"] if r64 else None,
+                     "fp32_vs_fp64": dict(precision_gap(u32, u64), steps_total=args.warmup + args.steps)
+                     if r64 else None}
     if r64:
         g64 = pairs / (r64["ms_per_step"] * 1e-3) / 1e9
         # the same dominant stage as the FP32-delta line (T2S3: its single sweep)

@@ -1,6 +1,8 @@
 """Build libdugks.so (HIP for gfx950) in-tree with hipcc."""
 from __future__ import annotations
 
+import glob
+import hashlib
 import os
 import shutil
 import subprocess
@@ -10,8 +12,15 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdugks.so")
-SOURCES = ["sweep.hip", "sweep_fast.hip", "sweep_large.hip", "aux.hip", "adjoint.hip", "api.cpp"]
 ARCH = "gfx950"
+# The two lattice kernel files are compiled once per (lattice, precision)
+# pair, each object holding the explicit instantiations of that pair, so the
+# eight heavy compilations run in parallel.
+LATTICE_VARIANTS = [(9, 1), (9, 0), (37, 1), (37, 0)]
+UNITS = ([("sweep.hip", lat, d) for lat, d in LATTICE_VARIANTS] +
+         [("sweep_fast.hip", lat, d) for lat, d in LATTICE_VARIANTS] +
+         [("sweep_large.hip", None, None), ("aux.hip", None, None), ("adjoint.hip", None, None),
+          ("dispatch.hip", None, None), ("api.cpp", None, None)])
 # -packed-fp32-ops: no packed FP32 instructions are generated.
 FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -33,23 +42,51 @@ def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def build(verbose: bool = False) -> str:
+def _unit_cmd(src, lat, delta, obj):
+    defs = [] if lat is None else [f"-DDK_LAT={lat}", f"-DDK_DELTA={delta}"]
+    return ([hipcc()] + FLAGS + EXTRA.get(src, []) + defs + ["-x", "hip", "-c", os.path.join(CSRC, src),
+                                                             "-o", obj])
+
+
+def _headers_digest():
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(CSRC, "*.h")) + [os.path.join(HERE, "..", "include", "dugks.h")]):
+        with open(path, "rb") as f:
+            h.update(os.path.basename(path).encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile every unit and link libdugks.so.  With incremental=True an
+    object is reused when its source, every header, the command and the
+    object are unchanged since it was built."""
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
+    digest = _headers_digest()
 
-    def compile_one(src):
-        obj = os.path.join(bdir, src + ".o")
-        lang = ["-x", "hip"]
-        cmd = [hipcc()] + FLAGS + EXTRA.get(src, []) + lang + ["-c", os.path.join(CSRC, src), "-o", obj]
+    def compile_one(unit):
+        src, lat, delta = unit
+        tag = src if lat is None else f"{src}.{lat}.{'f32' if delta else 'f64'}"
+        obj = os.path.join(bdir, tag + ".o")
+        cmd = _unit_cmd(src, lat, delta, obj)
+        stamp = obj + ".stamp"
+        with open(os.path.join(CSRC, src), "rb") as f:
+            key = hashlib.sha256(f.read() + (digest + "\0".join(cmd)).encode()).hexdigest()
+        if incremental and os.path.exists(obj) and os.path.exists(stamp):
+            with open(stamp) as f:
+                if f.read().strip() == key:
+                    return obj
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
-            raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
+            raise RuntimeError(f"hipcc failed for {tag}:\n{r.stdout}\n{r.stderr}")
         if verbose and r.stderr.strip():
             print(r.stderr, file=sys.stderr)
+        with open(stamp, "w") as f:
+            f.write(key)
         return obj
 
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(compile_one, SOURCES))
+    with ThreadPoolExecutor(max_workers=min(len(UNITS), os.cpu_count() or 8)) as ex:
+        objs = list(ex.map(compile_one, UNITS))
     tmp = OUT + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}"] + objs + ["-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -60,4 +97,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

@@ -19,8 +19,10 @@
 #include "dugks_internal.h"
 #include "lattices.h"
 
+#include <type_traits>
 #include <utility>
 
+#include "launchers.h"
 #include "sweep_common.h"
 
 namespace dk {
@@ -536,37 +538,6 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
     }(Seq{});
 }
 
-// On a uniform grid the fast-kind tiles form the rectangle of tile columns
-// [cx0, cx1) by tile rows [ry0, ry1); the general kind is the ring around it
-// (the tiles within two cells of a wall).  With on = 1 a general launch has
-// one block per ring tile: the rows below the rectangle, then the side tiles
-// of its rows, then the rows above, ng tiles in all.
-struct Ring {
-    int on, gx, cx0, cx1, ry0, ry1, ng;
-};
-
-__device__ __forceinline__ void ring_tile(const Ring &r, int nxcd, int &tx, int &ty)
-{
-    // XCD-aware: the blocks of one XCD take a contiguous run of ring tiles
-    const int per = r.ng / nxcd, rem = r.ng % nxcd;
-    const int x = blockIdx.x % nxcd, slot = blockIdx.x / nxcd;
-    const int b = x * per + (x < rem ? x : rem) + slot;
-    const int fx = r.cx1 - r.cx0, side = r.gx - fx;
-    const int nb = r.ry0 * r.gx, nm = (r.ry1 - r.ry0) * side;
-    if (b < nb) {
-        ty = b / r.gx;
-        tx = b % r.gx;
-    } else if (b - nb < nm) {
-        const int k = b - nb, c = k % side;
-        ty = r.ry0 + k / side;
-        tx = c < r.cx0 ? c : c + fx;
-    } else {
-        const int k = b - nb - nm;
-        ty = r.ry1 + k / r.gx;
-        tx = k % r.gx;
-    }
-}
-
 // Single instance: tiles from the block index (XCD-aware order); each kind of
 // tile is handled by its own instantiation.  MAXT bounds the block: at 256 (a
 // tile of up to 256 cells, one wave per SIMD) the compiler may use the whole
@@ -578,38 +549,15 @@ sweep_small(const SweepParams p, const double h, const S *__restrict__ X,
             const S *__restrict__ F, S *__restrict__ out, const S *__restrict__ coef, const Ring r)
 {
     int tx, ty;
-    if (GENERAL && r.on) ring_tile(r, p.nxcd, tx, ty);
+    if (GENERAL && r.on) ring_tile_of(r, p.nxcd, blockIdx.x, tx, ty);
     else tile_of_block(p, tx, ty);
     if (tile_is_fast(p, tx * p.tile_x, ty * p.tile_y, p.tile_x, p.tile_y) == GENERAL) return;
     sweep_small_body<Lat, S, DELTA, STAGE, GENERAL>(p, h, X, F, out, coef, tx, ty);
 }
 
-// The ring of general tiles of a uniform grid (Ring::on = 0 where every tile is
-// general, or none is).  Mirrors tile_is_fast per tile column and tile row.
 static Ring ring_of(const SweepParams &p)
 {
-    Ring r{0, 0, 0, 0, 0, 0, 0};
-    const int gx = (p.nx + p.tile_x - 1) / p.tile_x, gy = (p.ny + p.tile_y - 1) / p.tile_y;
-    if (!p.uniform) return r;
-    auto range = [](bool per, int g, int t, int n, int &a, int &b) {
-        a = g;
-        b = 0;
-        for (int k = 0; k < g; k++) {
-            const int i0 = k * t;
-            if (per || (i0 >= 2 && i0 + t <= n - 2)) {
-                a = k < a ? k : a;
-                b = k + 1;
-            }
-        }
-        if (b <= a) a = b = 0;
-    };
-    int cx0, cx1, ry0, ry1;
-    range(p.perx != 0, gx, p.tile_x, p.nx, cx0, cx1);
-    range(p.pery != 0, gy, p.tile_y, p.ny, ry0, ry1);
-    const long long nfast = (long long)(cx1 - cx0) * (ry1 - ry0);
-    if (nfast == 0) return r;
-    r = Ring{1, gx, cx0, cx1, ry0, ry1, (int)((long long)gx * gy - nfast)};
-    return r;
+    return ring_make(p.uniform != 0, p.perx != 0, p.pery != 0, p.nx, p.ny, p.tile_x, p.tile_y);
 }
 
 // Many instances in one launch: block b works on work[b] = (instance, tile x,
@@ -705,50 +653,45 @@ static hipError_t launch_batched_t(const SweepParams *P, const StageIO *io, cons
     return hipGetLastError();
 }
 
-hipError_t launch_stage_batched(int stage, int lat, bool delta, const SweepParams *P, const StageIO *io,
-                                const int4 *work_fast, int nfast, const int4 *work_gen, int ngen,
-                                int nthreads, size_t smem, hipStream_t s)
+// Entry points of one lattice and precision (declared in launchers.h; the
+// dispatch by value is in dispatch.hip).
+template <class Lat, class S, bool DELTA>
+hipError_t small_stage(int stage, const SweepParams &p, double h, const void *X, const void *F, void *out,
+                       const void *coef, hipStream_t s, int parts)
 {
-#define DUGKS_LB(LAT, S_, D_)                                                                   \
-    return stage == 0 ? launch_batched_t<LAT, S_, D_, 0>(P, io, work_fast, nfast, work_gen, ngen, \
-                                                         nthreads, smem, s)                     \
-                      : launch_batched_t<LAT, S_, D_, 1>(P, io, work_fast, nfast, work_gen, ngen, \
-                                                         nthreads, smem, s)
-    if (lat == 9) {
-        if (delta) DUGKS_LB(LatD2Q9, float, true);
-        DUGKS_LB(LatD2Q9, double, false);
-    }
-    if (lat == 37) {
-        if (delta) DUGKS_LB(LatD2Q37, float, true);
-        DUGKS_LB(LatD2Q37, double, false);
-    }
-#undef DUGKS_LB
-    return hipErrorInvalidValue;
+    return stage == 0 ? launch_t<Lat, S, DELTA, 0>(p, h, X, F, out, coef, s, parts)
+                      : launch_t<Lat, S, DELTA, 1>(p, h, X, F, out, coef, s, parts);
 }
 
-hipError_t set_stage_smem(int lat, bool delta, size_t bytes)
+template <class Lat, class S, bool DELTA>
+hipError_t small_stage_batched(int stage, const SweepParams *P, const StageIO *io, const int4 *work_fast,
+                               int nfast, const int4 *work_gen, int ngen, int nthreads, size_t smem,
+                               hipStream_t s)
 {
-    if (lat == 9) return delta ? smem_t<LatD2Q9, float, true>(bytes) : smem_t<LatD2Q9, double, false>(bytes);
-    if (lat == 37) return delta ? smem_t<LatD2Q37, float, true>(bytes) : smem_t<LatD2Q37, double, false>(bytes);
-    return hipErrorInvalidValue;
+    return stage == 0 ? launch_batched_t<Lat, S, DELTA, 0>(P, io, work_fast, nfast, work_gen, ngen, nthreads, smem, s)
+                      : launch_batched_t<Lat, S, DELTA, 1>(P, io, work_fast, nfast, work_gen, ngen, nthreads, smem, s);
 }
 
-hipError_t launch_stage(int stage, int lat, bool delta, const SweepParams &p, double h,
-                        const void *X, const void *F, void *out, const void *coef, hipStream_t s, int parts)
+template <class Lat, class S, bool DELTA>
+hipError_t small_smem(size_t bytes)
 {
-#define DUGKS_L(LAT, S_, D_)                                                              \
-    return stage == 0 ? launch_t<LAT, S_, D_, 0>(p, h, X, F, out, coef, s, parts)        \
-                      : launch_t<LAT, S_, D_, 1>(p, h, X, F, out, coef, s, parts)
-    if (lat == 9) {
-        if (delta) DUGKS_L(LatD2Q9, float, true);
-        DUGKS_L(LatD2Q9, double, false);
-    }
-    if (lat == 37) {
-        if (delta) DUGKS_L(LatD2Q37, float, true);
-        DUGKS_L(LatD2Q37, double, false);
-    }
-#undef DUGKS_L
-    return hipErrorInvalidValue;
+    return smem_t<Lat, S, DELTA>(bytes);
 }
+
+// The build compiles this file once per lattice and precision (DK_LAT = 9 or
+// 37, DK_DELTA = 1 for FP32-delta), so the four sets of kernels compile in
+// parallel.
+#if defined(DK_LAT) && defined(DK_DELTA)
+using InstLat = std::conditional_t<DK_LAT == 9, LatD2Q9, LatD2Q37>;
+using InstS = std::conditional_t<DK_DELTA != 0, float, double>;
+template hipError_t small_stage<InstLat, InstS, DK_DELTA != 0>(int, const SweepParams &, double, const void *,
+                                                                const void *, void *, const void *,
+                                                                hipStream_t, int);
+template hipError_t small_stage_batched<InstLat, InstS, DK_DELTA != 0>(int, const SweepParams *,
+                                                                        const StageIO *, const int4 *, int,
+                                                                        const int4 *, int, int, size_t,
+                                                                        hipStream_t);
+template hipError_t small_smem<InstLat, InstS, DK_DELTA != 0>(size_t);
+#endif
 
 }  // namespace dk

@@ -1,6 +1,7 @@
 // Device helpers shared by the small- and large-velocity-set sweep kernels.
 #pragma once
 #include "dugks_internal.h"
+#include "ring.h"
 
 namespace dk {
 
@@ -229,8 +230,7 @@ __device__ __forceinline__ void tile_of_block(const SweepParams &p, int &tx, int
 
 __device__ __forceinline__ bool tile_is_fast(const SweepParams &p, int i0, int j0, int TX, int TY)
 {
-    return p.uniform && (p.perx || (i0 >= 2 && i0 + TX <= p.nx - 2)) &&
-           (p.pery || (j0 >= 2 && j0 + TY <= p.ny - 2));
+    return tile_fast(p.uniform != 0, p.perx != 0, p.pery != 0, p.nx, p.ny, i0, j0, TX, TY);
 }
 
 }  // namespace dk

@@ -25,8 +25,10 @@
 
 #include "dugks_internal.h"
 #include "lattices.h"
+#include "launchers.h"
 #include "sweep_common.h"
 
+#include <type_traits>
 #include <utility>
 
 namespace dk {
@@ -508,20 +510,8 @@ static hipError_t fast_launch_batched_t(int stage, bool tf, const SweepParams *P
     return hipGetLastError();
 }
 
-// The shapes compiled: the ones the library and the tile tuner choose from.
-#define DUGKS_FAST_SHAPES(X) X(32, 8) X(16, 16) X(64, 4) X(8, 32)
-
-int fast_tile_index(int tx, int ty)
-{
-    int k = 0;
-#define DUGKS_FS(A, B) if (tx == A && ty == B) return k; k++;
-    DUGKS_FAST_SHAPES(DUGKS_FS)
-#undef DUGKS_FS
-    return -1;
-}
-
 template <class Lat, class S, bool DELTA>
-static hipError_t fast_smem_lat(int tx, int ty, size_t bytes)
+hipError_t fast_smem(int tx, int ty, size_t bytes)
 {
 #define DUGKS_FS(A, B) if (tx == A && ty == B) return fast_smem_t<Lat, S, DELTA, A, B>(bytes);
     DUGKS_FAST_SHAPES(DUGKS_FS)
@@ -529,18 +519,9 @@ static hipError_t fast_smem_lat(int tx, int ty, size_t bytes)
     return hipErrorInvalidValue;
 }
 
-hipError_t set_fast_smem(int lat, bool delta, int tx, int ty, size_t bytes)
-{
-    if (lat == 9) return delta ? fast_smem_lat<LatD2Q9, float, true>(tx, ty, bytes)
-                               : fast_smem_lat<LatD2Q9, double, false>(tx, ty, bytes);
-    if (lat == 37) return delta ? fast_smem_lat<LatD2Q37, float, true>(tx, ty, bytes)
-                                : fast_smem_lat<LatD2Q37, double, false>(tx, ty, bytes);
-    return hipErrorInvalidValue;
-}
-
 template <class Lat, class S, bool DELTA>
-static hipError_t fast_launch_lat(int stage, const SweepParams &p, double h, const void *X, const void *F,
-                                  void *out, const void *coef, hipStream_t s)
+hipError_t fast_stage(int stage, const SweepParams &p, double h, const void *X, const void *F, void *out,
+                      const void *coef, hipStream_t s)
 {
 #define DUGKS_FS(A, B) \
     if (p.tile_x == A && p.tile_y == B) return fast_launch_t<Lat, S, DELTA, A, B>(stage, p, h, X, F, out, coef, s);
@@ -549,19 +530,9 @@ static hipError_t fast_launch_lat(int stage, const SweepParams &p, double h, con
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_stage_fast(int stage, int lat, bool delta, const SweepParams &p, double h, const void *X,
-                             const void *F, void *out, const void *coef, hipStream_t s)
-{
-    if (lat == 9) return delta ? fast_launch_lat<LatD2Q9, float, true>(stage, p, h, X, F, out, coef, s)
-                               : fast_launch_lat<LatD2Q9, double, false>(stage, p, h, X, F, out, coef, s);
-    if (lat == 37) return delta ? fast_launch_lat<LatD2Q37, float, true>(stage, p, h, X, F, out, coef, s)
-                                : fast_launch_lat<LatD2Q37, double, false>(stage, p, h, X, F, out, coef, s);
-    return hipErrorInvalidValue;
-}
-
 template <class Lat, class S, bool DELTA>
-static hipError_t fast_batched_lat(int stage, int tx, int ty, bool tf, const SweepParams *P, const StageIO *io,
-                                   const int4 *work, int nwork, size_t smem, hipStream_t s)
+hipError_t fast_stage_batched(int stage, int tx, int ty, bool tf, const SweepParams *P, const StageIO *io,
+                              const int4 *work, int nwork, size_t smem, hipStream_t s)
 {
 #define DUGKS_FS(A, B) \
     if (tx == A && ty == B) return fast_launch_batched_t<Lat, S, DELTA, A, B>(stage, tf, P, io, work, nwork, smem, s);
@@ -570,17 +541,16 @@ static hipError_t fast_batched_lat(int stage, int tx, int ty, bool tf, const Swe
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_stage_fast_batched(int stage, int lat, bool delta, int tx, int ty, bool tf, const SweepParams *P,
-                                     const StageIO *io, const int4 *work, int nwork, size_t smem,
-                                     hipStream_t s)
-{
-    if (lat == 9)
-        return delta ? fast_batched_lat<LatD2Q9, float, true>(stage, tx, ty, tf, P, io, work, nwork, smem, s)
-                     : fast_batched_lat<LatD2Q9, double, false>(stage, tx, ty, tf, P, io, work, nwork, smem, s);
-    if (lat == 37)
-        return delta ? fast_batched_lat<LatD2Q37, float, true>(stage, tx, ty, tf, P, io, work, nwork, smem, s)
-                     : fast_batched_lat<LatD2Q37, double, false>(stage, tx, ty, tf, P, io, work, nwork, smem, s);
-    return hipErrorInvalidValue;
-}
+// The build compiles this file once per lattice and precision (see sweep.hip).
+#if defined(DK_LAT) && defined(DK_DELTA)
+using InstLat = std::conditional_t<DK_LAT == 9, LatD2Q9, LatD2Q37>;
+using InstS = std::conditional_t<DK_DELTA != 0, float, double>;
+template hipError_t fast_smem<InstLat, InstS, DK_DELTA != 0>(int, int, size_t);
+template hipError_t fast_stage<InstLat, InstS, DK_DELTA != 0>(int, const SweepParams &, double, const void *,
+                                                               const void *, void *, const void *, hipStream_t);
+template hipError_t fast_stage_batched<InstLat, InstS, DK_DELTA != 0>(int, int, int, bool, const SweepParams *,
+                                                                       const StageIO *, const int4 *, int,
+                                                                       size_t, hipStream_t);
+#endif
 
 }  // namespace dk
