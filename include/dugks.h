@@ -172,8 +172,9 @@ int dugks_sync(dugks_t *h);
  * The forward pass is run from f0 keeping the state every ckpt_every steps;
  * the reverse sweep recomputes each segment from its checkpoint, so device
  * memory grows as (nsteps/ckpt_every + ckpt_every) states plus about 14
- * double arrays of nq*nx*ny, allocated for the call and released before it
- * returns.  The adjoint arithmetic is double for both precisions (for
+ * double arrays of nq*nx*ny.  That workspace is allocated on the first call
+ * and kept by the handle (released by dugks_destroy); a later call that needs
+ * more replaces it.  The adjoint arithmetic is double for both precisions (for
  * DUGKS_FP32_DELTA it linearises around the FP32 trajectory).  No atomics:
  * results are bitwise reproducible.  The handle's state is left unchanged.
  * Periodic uniform grids and the T3S3 scheme only (else DUGKS_ENOTSUP); batch
@@ -181,6 +182,21 @@ int dugks_sync(dugks_t *h);
 int dugks_backward(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
                    const double *dL_drho, const double *dL_du,
                    double *dL_df0, double *dL_dtau, int mem);
+
+/* dugks_backward for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same computation and results, with its workspace carved out of a fixed
+ * device array of 128 MiB (one per device, held from the first handle created
+ * on it until the process ends) instead of allocated.  Every pointer is
+ * device memory; the caller passes inputs and outputs.  A call whose
+ * workspace (the checkpoints plus about 14 double arrays of nq*nx*ny, see
+ * dugks_backward) exceeds 128 MiB returns DUGKS_EINVAL and does nothing.
+ * Calls on one device share that array: calls that overlap in time on the
+ * same device (other threads, other streams) race and must be serialised by
+ * the caller.  The call synchronises the handle's stream before returning. */
+int dugks_backward_noalloc(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
+                           const double *dL_drho, const double *dL_du,
+                           double *dL_df0, double *dL_dtau);
 
 /* Batch of independent instances (uneven grids, velocity sets, relaxation
  * times and walls) stepped together: every dugks_step launches one kernel

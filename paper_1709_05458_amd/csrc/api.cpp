@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -41,6 +42,10 @@ struct dugks {
     int prof_max = 0, prof_n = 0;
     bool prof_on = false;
     std::string variant;
+    int device = 0;                      // device current at creation
+    std::vector<double> hxi;             // host copy of the velocities, [2][nq]
+    void *adj_ws = nullptr;              // dugks_backward workspace, kept between calls
+    size_t adj_ws_bytes = 0;
     // batch of instances (dugks_create_batch): the handle owns the instances
     // and steps them with batched launches replayed from captured graphs
     struct Batch;
@@ -112,6 +117,43 @@ static int upload(dugks *h, const T *src, size_t count, const T **dst)
 // ---------------------------------------------------------------------------
 // Lattice detection: xi_q == c * e_q for the compiled integer lattices.
 // ---------------------------------------------------------------------------
+
+// Fixed device workspace of dugks_backward_noalloc, for callers that cannot
+// allocate device memory.  Each device the library runs on holds its own copy
+// from the first handle created there until the process ends.  In host code
+// the array's name is not a device address: the address each device sees is
+// taken once per device with hipGetSymbolAddress (at handle creation) and only
+// that address is used.
+static constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static constexpr int kMaxDevices = 64;
+static char *g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+// Address of the scratch array on `device`, which must be the current device.
+static int scratch_resolve(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(DUGKS_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return DUGKS_OK;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(DUGKS_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = (char *)ptr;
+    return DUGKS_OK;
+}
+
+static int scratch_of(int device, char **base)
+{
+    if (device < 0 || device >= kMaxDevices) return fail(DUGKS_EDEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    *base = g_scratch_ptr[device];
+    if (!*base) return fail(DUGKS_EDEVICE, "no-allocation scratch not resolved on this device");
+    return DUGKS_OK;
+}
+
 static const int kD2Q9x[9] = {-1, -1, -1, 0, 0, 0, 1, 1, 1};
 static const int kD2Q9y[9] = {-1, 0, 1, -1, 0, 1, -1, 0, 1};
 static const int kD2Q37x[37] = {0, -1, 0, 0, 1, -1, -1, 1, 1, -2, 0, 0, 2, -2, -2, -1, -1, 1, 1,
@@ -338,6 +380,10 @@ int dugks_destroy(dugks_t *h)
         delete h->batch;
     }
     for (auto &e : h->ev) (void)hipEventDestroy(e);
+    if (h->adj_ws) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->adj_ws);
+    }
     for (void *p : h->allocs) (void)hipFree(p);
     delete h;
     return DUGKS_OK;
@@ -439,6 +485,7 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
 
     dugks *h = new dugks();
     h->stream = (hipStream_t)d->stream;
+    h->hxi.assign(d->xi, d->xi + 2 * (size_t)nq);
     h->delta = d->precision == DUGKS_FP32_DELTA;
     h->elem = h->delta ? 4 : 8;
     SweepParams &p = h->p;
@@ -617,6 +664,13 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     std::vector<int> sxo, syo;
     axis_tables(d->xf, d->nx, p.perx, dxl, dxr, sxo, sxd1, sxd2, ixd);
     axis_tables(d->yf, d->ny, p.pery, dyl, dyr, syo, syd1, syd2, iyd);
+    // first device work of the handle: the device it lives on, and that
+    // device's address of the no-allocation scratch
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        dugks_destroy(h);
+        return fail(DUGKS_EDEVICE, "hipGetDevice failed");
+    }
+    if ((rc = scratch_resolve(h->device))) { dugks_destroy(h); return rc; }
 #define UP(vec, dst)                                                        \
     if ((rc = upload(h, vec.data(), vec.size(), &dst))) { dugks_destroy(h); return rc; }
     UP(dxl, p.g.dxl) UP(dxr, p.g.dxr) UP(dyl, p.g.dyl) UP(dyr, p.g.dyr)
@@ -1342,155 +1396,223 @@ static int step_from(dugks *h, const void *X, void *Y)
     return DUGKS_OK;
 }
 
-// device workspace of one backward call, released (after the stream drains)
-// when the call returns
-struct Workspace {
-    hipStream_t s = nullptr;
-    std::vector<void *> bufs;
-    ~Workspace()
+// Device workspace of a backward call.  Every buffer is carved, 256-byte
+// aligned, out of one region; with base == nullptr the arena only measures
+// the bytes a call needs.
+struct Arena {
+    char *base = nullptr;
+    size_t used = 0;
+    void *take(size_t bytes)
     {
-        (void)hipStreamSynchronize(s);
-        for (void *b : bufs) (void)hipFree(b);
+        const size_t off = (used + 255) & ~(size_t)255;
+        used = off + (bytes ? bytes : 8);
+        return base ? (void *)(base + off) : nullptr;
     }
-    int raw(void **p, size_t bytes)
-    {
-        hipError_t e = hipMalloc(p, bytes ? bytes : 8);
-        if (e != hipSuccess) return fail(DUGKS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-        bufs.push_back(*p);
-        return DUGKS_OK;
-    }
-    int get(double **p, size_t count)
-    {
-        void *v = nullptr;
-        int rc = raw(&v, count * sizeof(double));
-        *p = (double *)v;
-        return rc;
-    }
+    double *dbl(size_t count) { return (double *)take(count * sizeof(double)); }
 };
+
+struct AdjBuffers {
+    std::vector<void *> ck, seg;   // checkpoints and the states of one segment
+    double *fh_d, *B, *M, *G_d, *B2, *M2, *lam_fbar, *dtf, *lamLs, *lamB, *lamF, *lam[2], *dtau, *tau, *cA, *cC;
+};
+
+static void adj_carve(Arena &ar, const dugks *h, int nseg, int k, AdjBuffers &b)
+{
+    const long long n = h->p.ncell;
+    const size_t nqn = (size_t)h->p.nq * n;
+    b.ck.assign(nseg + 1, nullptr);
+    b.seg.assign(k, nullptr);
+    for (auto &c : b.ck) c = ar.take(h->elem * nqn);
+    for (int t = 1; t < k; t++) b.seg[t] = ar.take(h->elem * nqn);
+    b.fh_d = ar.dbl(nqn);
+    b.B = ar.dbl(nqn);
+    b.M = ar.dbl(3 * n);
+    b.G_d = ar.dbl(nqn);
+    b.B2 = ar.dbl(nqn);
+    b.M2 = ar.dbl(3 * n);
+    b.lam_fbar = ar.dbl(2 * nqn);
+    b.dtf = ar.dbl(2 * n);
+    b.lamLs = ar.dbl(nqn);
+    b.lamB = ar.dbl(nqn);
+    b.lamF = ar.dbl(nqn);
+    b.lam[0] = ar.dbl(nqn);
+    b.lam[1] = ar.dbl(nqn);
+    b.dtau = ar.dbl(n);
+    b.tau = h->p.tau_field ? const_cast<double *>(h->p.tau) : ar.dbl(n);
+    b.cA = ar.dbl(24 * (size_t)h->p.nq);
+    b.cC = ar.dbl(24 * (size_t)h->p.nq);
+}
+
+static int backward_check(dugks *h, int nsteps, int ckpt_every)
+{
+    if (nsteps < 0 || ckpt_every < 1) return fail(DUGKS_EINVAL, "bad arguments");
+    if (h->batch) return fail(DUGKS_ENOTSUP, "backward of a batch handle");
+    if (h->p.t2) return fail(DUGKS_ENOTSUP, "the adjoint is written for the T3S3 scheme");
+    if (!h->p.perx || !h->p.pery || !h->p.uniform)
+        return fail(DUGKS_ENOTSUP, "the adjoint supports periodic uniform grids only");
+    return DUGKS_OK;
+}
+
+// Bytes of device workspace a backward call of nsteps steps needs.
+static size_t backward_bytes(const dugks *h, int nsteps, int ckpt_every)
+{
+    const int k = std::min(ckpt_every, std::max(nsteps, 1));
+    const int nseg = (nsteps + k - 1) / k;
+    Arena ar;
+    AdjBuffers b;
+    adj_carve(ar, h, nseg, k, b);
+    return ar.used;
+}
+
+// The reverse pass on device buffers, its workspace carved from `base`
+// (backward_bytes(h, nsteps, ckpt_every) bytes).  Allocates no device memory.
+static int backward_core(dugks *h, const double *f0, int nsteps, int ckpt_every, const double *dL_drho,
+                         const double *dL_du, double *dL_df0, double *dL_dtau, char *base)
+{
+    const SweepParams &p = h->p;
+    const long long n = p.ncell;
+    const int nq = p.nq;
+    const size_t nqn = (size_t)nq * n;
+    int rc;
+    const int k = std::min(ckpt_every, std::max(nsteps, 1));
+    const int nseg = (nsteps + k - 1) / k;
+    Arena ar;
+    ar.base = base;
+    AdjBuffers w;
+    adj_carve(ar, h, nseg, k, w);
+    // host sources of the asynchronous copies below; the call synchronises
+    // the stream before they go out of scope
+    std::vector<double> t0, a, c;
+    if (!p.tau_field) {
+        t0.assign(n, p.tau0);
+        HIPCHECK(hipMemcpyAsync(w.tau, t0.data(), sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
+    }
+    {
+        // interface window weights in double for both stages (the forward
+        // kernels of FP32 storage hold them in float)
+        const double dx = 1.0 / p.inv_dx, dy = 1.0 / p.inv_dy;
+        a = fast_coefs(h->hxi.data(), nq, dx, dy, h->h1, p.kappa);
+        c = fast_coefs(h->hxi.data(), nq, dx, dy, h->h2, p.kappa);
+        HIPCHECK(hipMemcpyAsync(w.cA, a.data(), sizeof(double) * a.size(), hipMemcpyHostToDevice, h->stream));
+        HIPCHECK(hipMemcpyAsync(w.cC, c.data(), sizeof(double) * c.size(), hipMemcpyHostToDevice, h->stream));
+    }
+    AdjArgs g{};
+    g.nx = p.nx;
+    g.ny = p.ny;
+    g.nq = nq;
+    g.n = n;
+    g.dt = p.dt;
+    g.RT = p.RT;
+    g.iRT = p.iRT;
+    g.idx = p.inv_dx;
+    g.idy = p.inv_dy;
+    g.xi = p.xi;
+    g.eta = p.eta;
+    g.w = p.w;
+    g.tau = w.tau;
+    g.cA = w.cA;
+    g.cC = w.cC;
+    g.h1 = h->h1;
+    g.h2 = h->h2;
+
+    // forward pass from f0, keeping the state at every k-th step and the last
+    HIPCHECK(launch_set_state(p, h->delta, f0, w.ck[0], h->stream));
+    for (int i = 0; i < nseg; i++) {
+        const int len = std::min(k, nsteps - i * k);
+        const void *X = w.ck[i];
+        for (int t = 0; t < len; t++) {
+            void *Y = t == len - 1 ? w.ck[i + 1] : w.seg[t + 1];
+            if ((rc = step_from(h, X, Y))) return rc;
+            X = Y;
+        }
+    }
+    // seed from the final state; the tau sensitivity accumulates from zero
+    HIPCHECK(hipMemsetAsync(w.dtau, 0, sizeof(double) * n, h->stream));
+    HIPCHECK(adj_launch_prep(g, h->delta, p.rho0, w.ck[nseg], w.ck[nseg], w.fh_d, w.B, w.M, w.G_d, w.B2, w.M2,
+                             h->stream));
+    HIPCHECK(adj_launch_seed(g, w.fh_d, dL_drho, dL_du, w.lam[0], h->stream));
+    int cur = 0;
+    // reverse sweep, one checkpoint segment at a time
+    for (int i = nseg - 1; i >= 0; i--) {
+        const int len = std::min(k, nsteps - i * k);
+        const void *X = w.ck[i];
+        for (int t = 0; t + 1 < len; t++) {
+            if ((rc = step_from(h, X, w.seg[t + 1]))) return rc;
+            X = w.seg[t + 1];
+        }
+        for (int t = len - 1; t >= 0; t--) {
+            const void *Xt = t == 0 ? w.ck[i] : w.seg[t];
+            if ((rc = stage_a_from(h, Xt))) return rc;
+            if ((rc = record(h, KC_ADJ_STEP, true))) return rc;
+            HIPCHECK(adj_launch_prep(g, h->delta, p.rho0, Xt, h->G, w.fh_d, w.B, w.M, w.G_d, w.B2, w.M2,
+                                     h->stream));
+            HIPCHECK(adj_launch_step(g, w.lam[cur], w.lam[1 - cur], w.fh_d, w.B, w.M, w.G_d, w.B2, w.M2,
+                                     w.lam_fbar, w.dtf, w.lamLs, w.lamB, w.lamF, w.dtau, h->stream));
+            if ((rc = record(h, KC_ADJ_STEP, false))) return rc;
+            cur = 1 - cur;
+        }
+    }
+    HIPCHECK(adj_launch_init(g, f0, w.lam[cur], dL_df0, w.dtau, h->stream));
+    if (dL_dtau)
+        HIPCHECK(hipMemcpyAsync(dL_dtau, w.dtau, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
+    // the any-size kernels keep the moments of the current state in mom_state
+    if (!h->lat) HIPCHECK(launch_state_moments(p, h->delta, h->state[h->cur], h->mom_state, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    (void)nqn;
+    return DUGKS_OK;
+}
 
 int dugks_backward(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
                    const double *dL_drho, const double *dL_du, double *dL_df0, double *dL_dtau,
                    int mem)
 {
-    if (!h || !f0 || !dL_du || !dL_df0 || nsteps < 0 || ckpt_every < 1)
-        return fail(DUGKS_EINVAL, "bad arguments");
-    if (h->batch) return fail(DUGKS_ENOTSUP, "backward of a batch handle");
-    if (h->p.t2) return fail(DUGKS_ENOTSUP, "the adjoint is written for the T3S3 scheme");
-    const SweepParams &p = h->p;
-    if (!p.perx || !p.pery || !p.uniform)
-        return fail(DUGKS_ENOTSUP, "the adjoint supports periodic uniform grids only");
-    const long long n = p.ncell;
-    const int nq = p.nq;
-    const size_t nqn = (size_t)nq * n;
-    int rc;
+    if (!h || !f0 || !dL_du || !dL_df0) return fail(DUGKS_EINVAL, "bad arguments");
+    int rc = backward_check(h, nsteps, ckpt_every);
+    if (rc) return rc;
+    const long long n = h->p.ncell;
+    const size_t nqn = (size_t)h->p.nq * n;
     Staged sf0, srho, su, sdf, sdt;
     if ((rc = stage_in(f0, nqn, mem, sf0, h->stream)) || (rc = stage_in(dL_du, 2 * n, mem, su, h->stream)))
         return rc;
     if (dL_drho && (rc = stage_in(dL_drho, n, mem, srho, h->stream))) return rc;
     if ((rc = stage_out(h, dL_df0, nqn, mem, sdf))) return rc;
     if (dL_dtau && (rc = stage_out(h, dL_dtau, n, mem, sdt))) return rc;
-
-    Workspace ws;
-    ws.s = h->stream;
-    const int k = std::min(ckpt_every, std::max(nsteps, 1));
-    const int nseg = (nsteps + k - 1) / k;
-    std::vector<void *> ck(nseg + 1), seg(k);
-    for (auto &b : ck)
-        if ((rc = ws.raw(&b, h->elem * nqn))) return rc;
-    for (int t = 1; t < k; t++)
-        if ((rc = ws.raw(&seg[t], h->elem * nqn))) return rc;
-    double *fh_d, *B, *M, *G_d, *B2, *M2, *lam_fbar, *dtf, *lamLs, *lamB, *lamF, *lam[2], *dtau, *tau, *cA,
-        *cC;
-    if ((rc = ws.get(&fh_d, nqn)) || (rc = ws.get(&B, nqn)) || (rc = ws.get(&M, 3 * n)) ||
-        (rc = ws.get(&G_d, nqn)) || (rc = ws.get(&B2, nqn)) || (rc = ws.get(&M2, 3 * n)) ||
-        (rc = ws.get(&lam_fbar, 2 * nqn)) || (rc = ws.get(&dtf, 2 * n)) || (rc = ws.get(&lamLs, nqn)) ||
-        (rc = ws.get(&lamB, nqn)) || (rc = ws.get(&lamF, nqn)) || (rc = ws.get(&lam[0], nqn)) ||
-        (rc = ws.get(&lam[1], nqn)) || (rc = ws.get(&dtau, n)) || (rc = ws.get(&cA, 24 * (size_t)nq)) ||
-        (rc = ws.get(&cC, 24 * (size_t)nq)))
+    // the workspace stays with the handle and grows when a call needs more
+    const size_t need = backward_bytes(h, nsteps, ckpt_every);
+    if (need > h->adj_ws_bytes) {
+        HIPCHECK(hipStreamSynchronize(h->stream));
+        if (h->adj_ws) (void)hipFree(h->adj_ws);
+        h->adj_ws = nullptr;
+        h->adj_ws_bytes = 0;
+        hipError_t e = hipMalloc(&h->adj_ws, need);
+        if (e != hipSuccess) {
+            h->adj_ws = nullptr;
+            return fail(DUGKS_ENOMEM, std::string("adjoint workspace: ") + hipGetErrorString(e));
+        }
+        h->adj_ws_bytes = need;
+    }
+    if ((rc = backward_core(h, sf0.dev, nsteps, ckpt_every, dL_drho ? srho.dev : nullptr, su.dev, sdf.dev,
+                            dL_dtau ? sdt.dev : nullptr, (char *)h->adj_ws)))
         return rc;
-    if (p.tau_field) {
-        tau = const_cast<double *>(p.tau);
-    } else {
-        if ((rc = ws.get(&tau, n))) return rc;
-        std::vector<double> t0(n, p.tau0);
-        HIPCHECK(hipMemcpyAsync(tau, t0.data(), sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
-        HIPCHECK(hipStreamSynchronize(h->stream));
-    }
-    {
-        // interface window weights in double for both stages (the forward
-        // kernels of FP32 storage hold them in float)
-        std::vector<double> xi(2 * (size_t)nq);
-        HIPCHECK(hipMemcpy(xi.data(), p.xi, sizeof(double) * nq, hipMemcpyDeviceToHost));
-        HIPCHECK(hipMemcpy(xi.data() + nq, p.eta, sizeof(double) * nq, hipMemcpyDeviceToHost));
-        const double dx = 1.0 / p.inv_dx, dy = 1.0 / p.inv_dy;
-        std::vector<double> a = fast_coefs(xi.data(), nq, dx, dy, h->h1, p.kappa);
-        std::vector<double> c = fast_coefs(xi.data(), nq, dx, dy, h->h2, p.kappa);
-        HIPCHECK(hipMemcpyAsync(cA, a.data(), sizeof(double) * a.size(), hipMemcpyHostToDevice, h->stream));
-        HIPCHECK(hipMemcpyAsync(cC, c.data(), sizeof(double) * c.size(), hipMemcpyHostToDevice, h->stream));
-        HIPCHECK(hipStreamSynchronize(h->stream));
-    }
-    AdjArgs a{};
-    a.nx = p.nx;
-    a.ny = p.ny;
-    a.nq = nq;
-    a.n = n;
-    a.dt = p.dt;
-    a.RT = p.RT;
-    a.iRT = p.iRT;
-    a.idx = p.inv_dx;
-    a.idy = p.inv_dy;
-    a.xi = p.xi;
-    a.eta = p.eta;
-    a.w = p.w;
-    a.tau = tau;
-    a.cA = cA;
-    a.cC = cC;
-    a.h1 = h->h1;
-    a.h2 = h->h2;
-
-    // forward pass from f0, keeping the state at every k-th step and the last
-    HIPCHECK(launch_set_state(p, h->delta, sf0.dev, ck[0], h->stream));
-    for (int i = 0; i < nseg; i++) {
-        const int len = std::min(k, nsteps - i * k);
-        const void *X = ck[i];
-        for (int t = 0; t < len; t++) {
-            void *Y = t == len - 1 ? ck[i + 1] : seg[t + 1];
-            if ((rc = step_from(h, X, Y))) return rc;
-            X = Y;
-        }
-    }
-    // seed from the final state
-    HIPCHECK(hipMemsetAsync(dtau, 0, sizeof(double) * n, h->stream));
-    HIPCHECK(adj_launch_prep(a, h->delta, p.rho0, ck[nseg], ck[nseg], fh_d, B, M, G_d, B2, M2, h->stream));
-    HIPCHECK(adj_launch_seed(a, fh_d, dL_drho ? srho.dev : nullptr, su.dev, lam[0], h->stream));
-    int cur = 0;
-    // reverse sweep, one checkpoint segment at a time
-    for (int i = nseg - 1; i >= 0; i--) {
-        const int len = std::min(k, nsteps - i * k);
-        const void *X = ck[i];
-        for (int t = 0; t + 1 < len; t++) {
-            if ((rc = step_from(h, X, seg[t + 1]))) return rc;
-            X = seg[t + 1];
-        }
-        for (int t = len - 1; t >= 0; t--) {
-            const void *Xt = t == 0 ? ck[i] : seg[t];
-            if ((rc = stage_a_from(h, Xt))) return rc;
-            if ((rc = record(h, KC_ADJ_STEP, true))) return rc;
-            HIPCHECK(adj_launch_prep(a, h->delta, p.rho0, Xt, h->G, fh_d, B, M, G_d, B2, M2, h->stream));
-            HIPCHECK(adj_launch_step(a, lam[cur], lam[1 - cur], fh_d, B, M, G_d, B2, M2, lam_fbar, dtf, lamLs,
-                                     lamB, lamF, dtau, h->stream));
-            if ((rc = record(h, KC_ADJ_STEP, false))) return rc;
-            cur = 1 - cur;
-        }
-    }
-    HIPCHECK(adj_launch_init(a, sf0.dev, lam[cur], sdf.dev, dtau, h->stream));
-    if (dL_dtau) HIPCHECK(hipMemcpyAsync(sdt.dev, dtau, sizeof(double) * n, hipMemcpyDeviceToDevice, h->stream));
-    // the any-size kernels keep the moments of the current state in mom_state
-    if (!h->lat) HIPCHECK(launch_state_moments(p, h->delta, h->state[h->cur], h->mom_state, h->stream));
     if ((rc = finish_out(h, dL_df0, nqn, mem, sdf))) return rc;
     if (dL_dtau && (rc = finish_out(h, dL_dtau, n, mem, sdt))) return rc;
-    HIPCHECK(hipStreamSynchronize(h->stream));
     return DUGKS_OK;
+}
+
+int dugks_backward_noalloc(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
+                           const double *dL_drho, const double *dL_du, double *dL_df0, double *dL_dtau)
+{
+    if (!h || !f0 || !dL_du || !dL_df0) return fail(DUGKS_EINVAL, "bad arguments");
+    int rc = backward_check(h, nsteps, ckpt_every);
+    if (rc) return rc;
+    const size_t need = backward_bytes(h, nsteps, ckpt_every);
+    if (need > kScratchBytes)
+        return fail(DUGKS_EINVAL, "dugks_backward_noalloc: the call needs " + std::to_string(need) +
+                                      " bytes of workspace, above the fixed scratch of " +
+                                      std::to_string(kScratchBytes) + " bytes");
+    char *base = nullptr;
+    if ((rc = scratch_of(h->device, &base))) return rc;
+    return backward_core(h, f0, nsteps, ckpt_every, dL_drho, dL_du, dL_df0, dL_dtau, base);
 }
 
 }  // extern "C"

@@ -69,6 +69,7 @@ def lib():
             "dugks_set_tau": ([vp, vp, ip], ip),
             "dugks_sync": ([vp], ip),
             "dugks_backward": ([vp, vp, ip, ip, vp, vp, vp, vp, ip], ip),
+            "dugks_backward_noalloc": ([vp, vp, ip, ip, vp, vp, vp, vp], ip),
             "dugks_prof_begin": ([vp, ip], ip),
             "dugks_prof_query": ([vp, ip, dp, POINTER(c_int)], ip),
             "dugks_prof_end": ([vp], ip),
@@ -338,6 +339,18 @@ class Solver:
         check(lib().dugks_backward(self.h, pf, int(nsteps), int(ckpt_every), pr, pu, pg, pt, mem),
               "dugks_backward")
         return gf, gt
+
+    def backward_noalloc(self, f0, nsteps: int, ckpt_every: int, dL_du, dL_df0, dL_drho=None, dL_dtau=None):
+        """dugks_backward_noalloc: the same gradients into caller-owned torch
+        device tensors (dL_df0 [q][y][x], dL_dtau [y][x] or None), with the
+        workspace in the library's fixed device scratch."""
+        for a in (f0, dL_du, dL_df0, dL_drho, dL_dtau):
+            if a is not None and not (_is_torch(a) and a.is_cuda):
+                raise ValueError("backward_noalloc takes torch device tensors only")
+        ptr = lambda a: None if a is None else _ptr_mem(a)[0]
+        check(lib().dugks_backward_noalloc(self.h, ptr(f0), int(nsteps), int(ckpt_every), ptr(dL_drho),
+                                           ptr(dL_du), ptr(dL_df0), ptr(dL_dtau)),
+              "dugks_backward_noalloc")
 
     # -- timing --------------------------------------------------------------
     def prof_begin(self, max_launches: int):
