@@ -27,10 +27,10 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 METRIC = "G cell\u00b7velocity updates/s per DUGKS step + %HBM peak, FP32-\u03b4f vs FP64"
 UNIT = "G cell\u00b7velocity updates/s"
 # sources whose change invalidates stored hardware-counter traffic of the sweep kernels
-KERNEL_SOURCES = ["sweep_fast.hip", "sweep_common.h", "lattices.h",
+KERNEL_SOURCES = ["sweep_fast.hip", "sweep_common.h", "lattices.h", "launchers.h", "ring.h",
                   "dugks_internal.h", "api.cpp", "../build.py"]   # (build flags shape the code too)
 # the same for the any-size kernels
-LQ_SOURCES = ["sweep_large.hip", "sweep_common.h", "dugks_internal.h", "api.cpp", "../build.py"]
+LQ_SOURCES = ["sweep_large.hip", "sweep_common.h", "ring.h", "dugks_internal.h", "api.cpp", "../build.py"]
 PROFILES = os.path.join(ROOT, "profiles")
 
 

@@ -32,6 +32,8 @@
 #ifndef DUGKS_H
 #define DUGKS_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -109,7 +111,47 @@ typedef struct {
     int scheme;             /* dugks_scheme; 0 = T3S3.  Both schemes take the
                              * dt/tau <= 12 guard; dugks_backward and batches take
                              * T3S3 only (DUGKS_ENOTSUP / DUGKS_EINVAL) */
+    /* --- relaxation time from the Knudsen number (paper, "Numerical tests":
+     * Kn = lambda / L with the mean free path lambda = tau sqrt(pi RT / 2)):
+     * used when tau == NULL and tau0 <= 0; then tau0 = kn * l_ref / sqrt(pi RT / 2). */
+    double kn;
+    double l_ref;
+    /* --- variants of the paper's method, run by separate kernels that follow
+     * the computational sequence step by step (FP64 storage, uniform periodic
+     * grids; otherwise DUGKS_ENOTSUP):
+     * family_a: the member a of the time-discretization family (section "Time
+     *   discretization": A = a/2, K from A = (3K-2)/(6K-3), eq. EEWithP with
+     *   P_n, P', P_{n+1}); 0 selects 1/3, the paper's T3S3; other values must
+     *   lie in (1/3, 1/2].  The stored state is f - P_{n+1} dt Omega.
+     * reconstruction: dugks_reconstruction. */
+    double family_a;
+    int reconstruction;
+    /* --- device memory of the handle's buffers: when dev_alloc is not NULL the
+     * library takes every buffer it keeps (state, tables, workspaces) from
+     * dev_alloc(bytes, alloc_ctx) and returns it with dev_free(ptr, alloc_ctx)
+     * (for example a caching allocator); a NULL return fails with
+     * DUGKS_ENOMEM.  Temporary staging of host arrays still uses the runtime
+     * allocator. */
+    void *(*dev_alloc)(size_t bytes, void *ctx);
+    void (*dev_free)(void *ptr, void *ctx);
+    void *alloc_ctx;
 } dugks_desc;
+
+/* Interface reconstructions (dugks_desc.reconstruction).  POINT is the
+ * library's reading of eq. flux_DS: cell values as centre values, one
+ * midpoint per face for eq. microflux.  CELL_AVERAGE reads the cell values
+ * as cell averages (the paper's definition of f_j), reconstructs the
+ * quadratic whose cell averages match them, and integrates each face with the
+ * two-point Gauss rule (recovery, eq. recover2f, at each Gauss point).  S2 is
+ * the original DUGKS reconstruction the paper compares with (its reference
+ * for the second-order scheme): linear interpolation at the face centre minus
+ * xi h times the face gradient.  With DUGKS_SCHEME_T2S3, S2 gives the paper's
+ * T2S2 scheme. */
+enum dugks_reconstruction {
+    DUGKS_RECON_POINT = 0,
+    DUGKS_RECON_CELL_AVERAGE = 1,
+    DUGKS_RECON_S2 = 2
+};
 
 /* Build a solver for one grid / velocity set / relaxation field (paper:
  * finite-volume grid, discrete velocity sets, BGK relaxation time, walls).
@@ -138,25 +180,46 @@ int dugks_set_state(dugks_t *h, const double *f, int mem);
 int dugks_init_equilibrium(dugks_t *h, const double *rho, const double *ux,
                            const double *uy, int mem);
 
-/* Advance nsteps steps of the handle's scheme (asynchronous on the stream). */
+/* Advance nsteps steps of the handle's scheme (asynchronous on the stream).
+ * Lattice handles (D2Q9 / D2Q37 kernels) replay each step from a HIP graph
+ * captured at the second call (one graph per parity of the ping-pong state);
+ * the first call, and every call while kernel timing is on, launches the
+ * kernels directly.  Both give the same bits. */
 int dugks_step(dugks_t *h, int nsteps);
 
-/* Cell density and velocity [cell] of the current state (moments of fhat,
- * which equal those of f for moment-exact weights). */
+/* Cell density and velocity [cell] of the current state: rho = sum_q f_q,
+ * rho u = sum_q xi_q f_q (paper, section "Discrete particle velocities", the
+ * moments of the discrete distribution), taken of fhat, whose moments equal
+ * those of f because the collision conserves them (the definitions under eq.
+ * feqIntD3rdHat2) when the weights are moment-exact.  Outputs are caller-owned,
+ * NULL to skip one; mem == DUGKS_MEM_HOST synchronises the stream.  Errors:
+ * DUGKS_EINVAL (null handle, bad mem), DUGKS_ENOMEM (host staging). */
 int dugks_moments(dugks_t *h, double *rho, double *ux, double *uy, int mem);
 
-/* Physical distribution f = (4 tau fhat + dt E) / (4 tau + dt), [q][cell]
- * (T2S3: f = (2 tau ftilde + dt E) / (2 tau + dt)). */
+/* Physical distribution f = (4 tau fhat + dt E) / (4 tau + dt), [q][cell],
+ * the inverse of fhat = f - (dt/4) Omega (paper, definitions under eq.
+ * feqIntD3rdHat2, and the fhat^+ relation that follows them; T2S3:
+ * f = (2 tau ftilde + dt E) / (2 tau + dt), Remark I; family member a:
+ * f = (tau fhat + P_{n+1} dt E) / (tau + P_{n+1} dt)).  f is caller-owned. */
 int dugks_get_state(dugks_t *h, double *f, int mem);
 
 /* The stored variable (fhat, or ftilde for T2S3) itself, [q][cell], in double. */
 int dugks_get_fhat(dugks_t *h, double *fhat, int mem);
 
-/* Replace the relaxation-time field ([cell], > 0, dt/tau <= 12). */
+/* Replace the relaxation-time field ([cell], > 0, dt/tau <= 12: the paper's
+ * stability bound at a = 1/3, section "Time discretization").  The BGK
+ * relaxation time of Omega = -(f - f^eq)/tau (eq. BE and below); only
+ * handles created with a tau field (desc.tau != NULL) take it (else
+ * DUGKS_EINVAL); DUGKS_EUNSTABLE if a value breaks the bound. */
 int dugks_set_tau(dugks_t *h, const double *tau, int mem);
 
-/* Block until all queued work of h is done; reports DUGKS_ENONFINITE if the
- * density of the current state is not finite anywhere. */
+/* Block until all queued work of h is done; reports DUGKS_ENONFINITE if a
+ * stage wrote a non-finite value since the last dugks_sync.  The stage kernels
+ * test one velocity of every cell they write and raise a device flag; a
+ * non-finite value reaches every velocity of its cell and of its neighbours
+ * through the cell and interface moments in the next stage, so it is flagged
+ * at the latest one stage after it appears.  The flag is cleared by the
+ * call. */
 int dugks_sync(dugks_t *h);
 
 /* Discrete adjoint (not part of the paper's method): the exact gradient of

@@ -39,7 +39,12 @@ class _OcCase(ctypes.Structure):
                 ("RT", c_double), ("dt", c_double),
                 ("bc", c_int * 4), ("uw", (c_double * 2) * 4),
                 ("literal_ftilde", c_int), ("literal_fbp", c_int),
-                ("literal_taylor", c_int)]
+                ("literal_taylor", c_int), ("recon", c_int), ("a_param", c_double)]
+
+# interface reconstructions (dugks_oracle.c, "Variants"): point values with
+# the midpoint face rule (the paper's choice), cell averages with the two-point
+# Gauss rule, and the original DUGKS linear reconstruction S2
+RECON_POINT, RECON_CELL_AVERAGE, RECON_S2 = 0, 1, 2
 
 
 _libs = {}
@@ -67,7 +72,7 @@ class Oracle:
 
     def __init__(self, case, complex_step: bool = False, literal_ftilde: bool = False,
                  literal_fbp: bool = False, literal_taylor: bool = True,
-                 dt: float | None = None):
+                 dt: float | None = None, recon: int = RECON_POINT, a_param: float = 1.0 / 3.0):
         self.case = case
         self.cs = complex_step
         self.dtype = np.complex128 if complex_step else np.float64
@@ -95,6 +100,8 @@ class Oracle:
         c.literal_ftilde = int(literal_ftilde)
         c.literal_fbp = int(literal_fbp)
         c.literal_taylor = int(literal_taylor)
+        c.recon = int(recon)
+        c.a_param = float(a_param)
         self.c = c
         self.shape_q = (vs.nq, g.ny, g.nx)
         self.shape_c = (g.ny, g.nx)
@@ -145,6 +152,19 @@ class Oracle:
                                 _ptr(fx), _ptr(fy))
         return fx, fy
 
+    def face_point_values(self, B, rho_cell, h):
+        """Interface values at the face quadrature points of the variant
+        readings: fx [q][point][y][x-face], fy [q][point][y-face][x]."""
+        B = self._arr(B, self.shape_q)
+        rho_cell = self._arr(rho_cell, self.shape_c)
+        nq, ny, nx = self.shape_q
+        npt = 2 if self.c.recon == RECON_CELL_AVERAGE else 1
+        fx = np.zeros((nq, npt, ny, nx + 1), dtype=self.dtype)
+        fy = np.zeros((nq, npt, ny + 1, nx), dtype=self.dtype)
+        self._fn("face_point_values")(ctypes.byref(self.c), _ptr(B), _ptr(rho_cell), c_double(h),
+                                      _ptr(fx), _ptr(fy))
+        return fx, fy
+
     def flux(self, B, rho_cell, h):
         B = self._arr(B, self.shape_q)
         rho_cell = self._arr(rho_cell, self.shape_c)
@@ -170,6 +190,42 @@ class Oracle:
         self._check(self._fn("t3s3_run")(ctypes.byref(self.c), _ptr(self.tau), _ptr(fhat), c_int(nsteps)))
         return fhat
 
+    # -- the time-discretization family (member a_param) ----------------------
+    def step_a(self, fhat):
+        fhat = self._arr(fhat, self.shape_q)
+        out = np.empty_like(fhat)
+        self._check(self._fn("t3a_step")(ctypes.byref(self.c), _ptr(self.tau), _ptr(fhat), _ptr(out)))
+        return out
+
+    def run_a(self, fhat, nsteps: int):
+        fhat = self._arr(fhat, self.shape_q).copy()
+        self._check(self._fn("t3a_run")(ctypes.byref(self.c), _ptr(self.tau), _ptr(fhat), c_int(nsteps)))
+        return fhat
+
+    def f_to_fhat_a(self, f):
+        f = self._arr(f, self.shape_q)
+        out = np.empty_like(f)
+        self._check(self._fn("f_to_fhat_a")(ctypes.byref(self.c), _ptr(self.tau), _ptr(f), _ptr(out)))
+        return out
+
+    def fhat_to_f_a(self, fhat):
+        fhat = self._arr(fhat, self.shape_q)
+        out = np.empty_like(fhat)
+        self._check(self._fn("fhat_to_f_a")(ctypes.byref(self.c), _ptr(self.tau), _ptr(fhat), _ptr(out)))
+        return out
+
+    def f_to_ftilde(self, f, delta: float):
+        f = self._arr(f, self.shape_q)
+        out = np.empty_like(f)
+        self._check(self._fn("f_to_ftilde")(ctypes.byref(self.c), _ptr(self.tau), c_double(delta),
+                                            _ptr(f), _ptr(out)))
+        return out
+
+    def t2_run(self, ft, delta: float, nsteps: int):
+        for _ in range(nsteps):
+            ft = self.t2_step(ft, delta)
+        return ft
+
     def t2_step(self, ft, delta: float):
         ft = self._arr(ft, self.shape_q)
         out = np.empty_like(ft)
@@ -193,6 +249,8 @@ class Oracle:
 
     @staticmethod
     def _check(rc):
+        if rc == -2:
+            raise ValueError("the S2 reconstruction of the oracle takes periodic grids only")
         if rc != 0:
             raise MemoryError("oracle allocation failed")
 
@@ -200,30 +258,39 @@ class Oracle:
 # ---------------------------------------------------------------------------
 # numpy helpers used by the pin tests (test infrastructure as well)
 # ---------------------------------------------------------------------------
-def chapman_enskog_tgv(case, t: float = 0.0):
+def chapman_enskog_tgv(case, t: float = 0.0, cell_average: bool = False):
     """Initial distribution of the Taylor-Green case by the Navier-Stokes
     Chapman-Enskog form f = f^eq - tau (d_t f^eq + xi . grad f^eq) (paper,
     Taylor vortex flow section), with rho, u and their space/time derivatives
-    taken analytically from the Taylor-Green solution."""
+    taken analytically from the Taylor-Green solution.  With cell_average
+    (uniform grids) every Fourier mode of the fields is replaced by its
+    average over the cell (to second order in the amplitude, the cell
+    average of f)."""
     g, vs = case.grid, case.vs
     u0, A, B, nu = (case.meta[k] for k in ("u0", "A", "B", "nu"))
     RT, rho0 = vs.RT, case.rho0
     X, Y = np.meshgrid(g.xc, g.yc)
     al = A * A + B * B
     d = np.exp(-nu * al * t)
-    ux = -(u0 / A) * np.cos(A * X) * np.sin(B * Y) * d
-    uy = (u0 / B) * np.sin(A * X) * np.cos(B * Y) * d
-    p = -(u0 ** 2 / 4) * (np.cos(2 * A * X) / A ** 2 + np.cos(2 * B * Y) / B ** 2) * d * d
+    if cell_average:
+        hx, hy = 0.5 * (g.xf[1] - g.xf[0]), 0.5 * (g.yf[1] - g.yf[0])
+        s1 = np.sinc(A * hx / np.pi) * np.sinc(B * hy / np.pi)   # modes of A x and B y
+        sx2, sy2 = np.sinc(2 * A * hx / np.pi), np.sinc(2 * B * hy / np.pi)
+    else:
+        s1 = sx2 = sy2 = 1.0
+    ux = -(u0 / A) * np.cos(A * X) * np.sin(B * Y) * d * s1
+    uy = (u0 / B) * np.sin(A * X) * np.cos(B * Y) * d * s1
+    p = -(u0 ** 2 / 4) * (np.cos(2 * A * X) / A ** 2 * sx2 + np.cos(2 * B * Y) / B ** 2 * sy2) * d * d
     rho = rho0 + p / RT
     # derivatives
-    ux_x = u0 * np.sin(A * X) * np.sin(B * Y) * d
-    ux_y = -(u0 * B / A) * np.cos(A * X) * np.cos(B * Y) * d
-    uy_x = (u0 * A / B) * np.cos(A * X) * np.cos(B * Y) * d
-    uy_y = -u0 * np.sin(A * X) * np.sin(B * Y) * d
+    ux_x = u0 * np.sin(A * X) * np.sin(B * Y) * d * s1
+    ux_y = -(u0 * B / A) * np.cos(A * X) * np.cos(B * Y) * d * s1
+    uy_x = (u0 * A / B) * np.cos(A * X) * np.cos(B * Y) * d * s1
+    uy_y = -u0 * np.sin(A * X) * np.sin(B * Y) * d * s1
     ux_t = -nu * al * ux
     uy_t = -nu * al * uy
-    p_x = (u0 ** 2 / 2) * np.sin(2 * A * X) / A * d * d
-    p_y = (u0 ** 2 / 2) * np.sin(2 * B * Y) / B * d * d
+    p_x = (u0 ** 2 / 2) * np.sin(2 * A * X) / A * d * d * sx2
+    p_y = (u0 ** 2 / 2) * np.sin(2 * B * Y) / B * d * d * sy2
     p_t = -2 * nu * al * p
     r_x, r_y, r_t = p_x / RT, p_y / RT, p_t / RT
     nq = vs.nq

@@ -48,6 +48,25 @@
  *  R7 (varying tau): the interface relaxation time is the mean of the two
  *     adjacent cells' values; at a wall, the interior cell's value.
  *  R8: the micro-flux carries the minus sign of L(f) = -xi . grad f.
+ *
+ * Variants selected by the case (not the paper's default choices):
+ *  recon = 1 (cell averages, section "Space discretization"): the cell values
+ *     are read as cell averages, as the paper defines f_j; the quadratic
+ *     about the upwind cell is the one whose cell averages over the 3-point
+ *     stencils match the data (exact for quadratic fields), and each face
+ *     integral of eq. microflux takes the two-point Gauss rule instead of the
+ *     midpoint rule the paper keeps.  Interface recovery (eq. recover2f) is
+ *     done at each Gauss point.
+ *  recon = 2 (S2, the original DUGKS reconstruction the paper compares with,
+ *     cited from its reference [guo2013discrete]): the value at the foot
+ *     point x_b - xi h is the linear interpolation at the face centre minus
+ *     xi h times the gradient at the face (normal part from the two adjacent
+ *     centres, tangential part the mean of their central differences).
+ *     Periodic grids only.
+ *  a_param in (1/3, 1/2] (general member of the paper's family, section
+ *     "Time discretization"): t3a_step takes A = a/2, K from A = (3K-2)/(6K-3),
+ *     the coefficients P_n, P', P_{n+1} and the flux weights 3(2K-1)^2 and 1
+ *     over 4(3K^2 - 3K + 1); the state is fhat = f - P_{n+1} dt Omega.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -82,6 +101,8 @@ typedef struct {
     int literal_ftilde; /* pin-test switch, see R1 */
     int literal_fbp;    /* pin-test switch, see R2 */
     int literal_taylor; /* 1: expansion as printed (no 1/2), see R3 */
+    int recon;          /* 0: point values, midpoint faces; 1: cell averages, 2-point Gauss; 2: S2 */
+    double a_param;     /* member of the time-discretization family (t3a_step) */
 } oc_case;
 
 #define XI(c, q) ((c)->xi[(q)])
@@ -210,6 +231,139 @@ static real expand(const oc_case *c, const real *B, int iu, int ju,
     real B0 = B[(long)ju * nx + iu];
     double half = c->literal_taylor ? 1.0 : 0.5;
     return B0 + dx * Bx + dy * By + half * (dx * dx * Bxx + 2.0 * dx * dy * Bxy + dy * dy * Byy);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cell-average reading (recon = 1).  Along one axis, the weights d0, d1, d2 */
+/* over the same three cells as axis_stencil give the value, first and      */
+/* second derivative at the own centre of the quadratic whose averages over */
+/* those cells equal the data: for a cell at centre offset p with width w, */
+/* the averages of 1, x, x^2 are 1, p, p^2 + w^2/12.                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int off[3];
+    double d0[3], d1[3], d2[3];
+} stencil3a;
+
+static double width(const double *f, int n, int i)
+{
+    int k = i;
+    while (k < 0) k += n;
+    while (k >= n) k -= n;
+    return f[k + 1] - f[k];
+}
+
+/* solve the 3x3 system sum_k d[k] M[k][m] = rhs[m] (Cramer's rule) */
+static void solve3t(double M[3][3], const double rhs[3], double d[3])
+{
+    double A[3][3];
+    for (int m = 0; m < 3; m++)
+        for (int k = 0; k < 3; k++) A[m][k] = M[k][m];
+    double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                 A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                 A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    for (int k = 0; k < 3; k++) {
+        double B[3][3];
+        for (int m = 0; m < 3; m++)
+            for (int l = 0; l < 3; l++) B[m][l] = l == k ? rhs[m] : A[m][l];
+        d[k] = (B[0][0] * (B[1][1] * B[2][2] - B[1][2] * B[2][1]) -
+                B[0][1] * (B[1][0] * B[2][2] - B[1][2] * B[2][0]) +
+                B[0][2] * (B[1][0] * B[2][1] - B[1][1] * B[2][0])) / det;
+    }
+}
+
+static stencil3a axis_stencil_avg(const double *f, int n, int periodic, int i)
+{
+    stencil3a s;
+    int o0 = -1;
+    if (!periodic) {
+        if (i == 0) o0 = 0;
+        else if (i == n - 1) o0 = -2;
+    }
+    double M[3][3];
+    double xc = centre(f, n, i);
+    for (int k = 0; k < 3; k++) {
+        s.off[k] = o0 + k;
+        double p = centre(f, n, i + o0 + k) - xc, w = width(f, n, i + o0 + k);
+        M[k][0] = 1.0;
+        M[k][1] = p;
+        M[k][2] = p * p + w * w / 12.0;
+    }
+    const double e0[3] = {1, 0, 0}, e1[3] = {0, 1, 0}, e2[3] = {0, 0, 2};
+    solve3t(M, e0, s.d0);
+    solve3t(M, e1, s.d1);
+    solve3t(M, e2, s.d2);
+    return s;
+}
+
+/* Value at (cell (iu,ju)) + (dx,dy) of the quadratic reconstructed from the */
+/* cell averages around the upwind cell; the quadratic term carries the same */
+/* coefficient as the point-value form (1/2 gives the exact quadratic).      */
+/* (sxa, sya: the stencils of every column and row, axis_stencil_avg) */
+static real expand_avg(const oc_case *c, const stencil3a *sxa, const stencil3a *sya, const real *B,
+                       int iu, int ju, double dx, double dy)
+{
+    int nx = c->nx, ny = c->ny;
+    stencil3a sx = sxa[iu], sy = sya[ju];
+    real V = 0, Bx = 0, Bxx = 0, By = 0, Byy = 0, Bxy = 0;
+    for (int k = 0; k < 3; k++) {
+        real v = B[(long)ju * nx + wrap(iu + sx.off[k], nx)];
+        V += sx.d0[k] * v;
+        Bx += sx.d1[k] * v;
+        Bxx += sx.d2[k] * v;
+    }
+    for (int k = 0; k < 3; k++) {
+        real v = B[(long)wrap(ju + sy.off[k], ny) * nx + iu];
+        By += sy.d1[k] * v;
+        Byy += sy.d2[k] * v;
+    }
+    for (int k = 0; k < 3; k++)
+        for (int l = 0; l < 3; l++)
+            Bxy += sx.d1[k] * sy.d1[l] *
+                   B[(long)wrap(ju + sy.off[l], ny) * nx + wrap(iu + sx.off[k], nx)];
+    /* the row average along x still holds the y-curvature over the own cell */
+    double wy = width(c->yf, ny, ju);
+    V -= wy * wy / 24.0 * Byy;
+    double half = c->literal_taylor ? 1.0 : 0.5;
+    return V + dx * Bx + dy * By + half * (dx * dx * Bxx + 2.0 * dx * dy * Bxy + dy * dy * Byy);
+}
+
+/* S2 (recon = 2): fbar^+(x_b - xi h) at a face between cells L and R along */
+/* axis `ax` (0: x-face, 1: y-face), periodic grids.                         */
+static real s2_value(const oc_case *c, const real *B, int ax, int iL, int jL, int iR, int jR,
+                     double ex, double ey, double h)
+{
+    int nx = c->nx, ny = c->ny;
+    real bL = B[(long)jL * nx + iL], bR = B[(long)jR * nx + iR];
+    real grad_n, grad_t;
+    if (ax == 0) {
+        double d = 0.5 * (width(c->xf, nx, iL) + width(c->xf, nx, iR));
+        grad_n = (bR - bL) / d;
+        stencil3 tL = axis_stencil(c->yf, ny, 1, jL), tR = axis_stencil(c->yf, ny, 1, jR);
+        real gL = 0, gR = 0;
+        for (int k = 0; k < 3; k++) {
+            gL += tL.d1[k] * B[(long)wrap(jL + tL.off[k], ny) * nx + iL];
+            gR += tR.d1[k] * B[(long)wrap(jR + tR.off[k], ny) * nx + iR];
+        }
+        grad_t = 0.5 * (gL + gR);
+        /* linear interpolation to the face centre */
+        double wl = 0.5 * width(c->xf, nx, iL), wr = 0.5 * width(c->xf, nx, iR);
+        real fb = (wr * bL + wl * bR) / (wl + wr);
+        return fb - ex * h * grad_n - ey * h * grad_t;
+    } else {
+        double d = 0.5 * (width(c->yf, ny, jL) + width(c->yf, ny, jR));
+        grad_n = (bR - bL) / d;
+        stencil3 tL = axis_stencil(c->xf, nx, 1, iL), tR = axis_stencil(c->xf, nx, 1, iR);
+        real gL = 0, gR = 0;
+        for (int k = 0; k < 3; k++) {
+            gL += tL.d1[k] * B[(long)jL * nx + wrap(iL + tL.off[k], nx)];
+            gR += tR.d1[k] * B[(long)jR * nx + wrap(iR + tR.off[k], nx)];
+        }
+        grad_t = 0.5 * (gL + gR);
+        double wl = 0.5 * width(c->yf, ny, jL), wr = 0.5 * width(c->yf, ny, jR);
+        real fb = (wr * bL + wl * bR) / (wl + wr);
+        return fb - ey * h * grad_n - ex * h * grad_t;
+    }
 }
 
 /* ------------------------------------------------------------------------ */
@@ -359,6 +513,192 @@ void OC(face_values)(const oc_case *c, const real *B, const real *rho_cell,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Interface values at the face quadrature points of the variants: recon 1  */
+/* (cell averages, two Gauss points per face at the centre -/+ half width / */
+/* sqrt 3) and recon 2 (S2, the face centre).  fx: [nq][npt][ny][nx+1],     */
+/* fy: [nq][npt][ny+1][nx].                                                 */
+/* ------------------------------------------------------------------------ */
+static void recover_faces(const oc_case *c, real *fb, long nf, long face, real tau_b, double h);
+
+static int face_points(const oc_case *c)
+{
+    return c->recon == 1 ? 2 : 1;
+}
+
+void OC(face_point_values)(const oc_case *c, const real *B, const real *rho_cell, double h,
+                           real *fx, real *fy)
+{
+    int nx = c->nx, ny = c->ny, nq = c->nq, npt = face_points(c);
+    long ncell = (long)nx * ny;
+    long nfx = (long)ny * (nx + 1), nfy = (long)(ny + 1) * nx;
+    int perx = c->bc[WEST] == BC_PERIODIC, pery = c->bc[SOUTH] == BC_PERIODIC;
+    const double g = 1.0 / sqrt(3.0);
+    stencil3a *sxa = malloc(sizeof(stencil3a) * nx), *sya = malloc(sizeof(stencil3a) * ny);
+    if (!sxa || !sya) { free(sxa); free(sya); return; }
+    for (int i = 0; i < nx; i++) sxa[i] = axis_stencil_avg(c->xf, nx, perx, i);
+    for (int j = 0; j < ny; j++) sya[j] = axis_stencil_avg(c->yf, ny, pery, j);
+
+    /* x-faces */
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; j++) {
+        double yc = centre(c->yf, ny, j), hy = 0.5 * width(c->yf, ny, j);
+        for (int fi = 0; fi <= nx; fi++) {
+            double xb = c->xf[fi];
+            int wallW = (fi == 0 && !perx), wallE = (fi == nx && !perx);
+            long fidx = (long)j * (nx + 1) + fi;
+            for (int pt = 0; pt < npt; pt++) {
+                double yb = npt == 2 ? yc + (pt == 0 ? -g : g) * hy : yc;
+                real *fp = fx + (long)pt * nfx + fidx;   /* stride between q: npt * nfx */
+                long st = (long)npt * nfx;
+                for (int q = 0; q < nq; q++) {
+                    const real *Bq = B + q * ncell;
+                    double ex = XI(c, q), ey = ETA(c, q);
+                    real v;
+                    if (c->recon == 2) {
+                        v = s2_value(c, Bq, 0, wrap(fi - 1, nx), j, wrap(fi, nx), j, ex, ey, h);
+                    } else {
+                        double dy = yb - ey * h - yc;
+                        if (wallW) {
+                            if (ex > 0.0) continue;
+                            v = expand_avg(c, sxa, sya, Bq, 0, j, xb - ex * h - centre(c->xf, nx, 0), dy);
+                        } else if (wallE) {
+                            if (ex < 0.0) continue;
+                            v = expand_avg(c, sxa, sya, Bq, nx - 1, j, xb - ex * h - centre(c->xf, nx, nx - 1), dy);
+                        } else {
+                            int iL = fi - 1, iR = fi;
+                            if (ex > 0.0) {
+                                v = expand_avg(c, sxa, sya, Bq, wrap(iL, nx), j, xb - ex * h - centre(c->xf, nx, iL), dy);
+                            } else if (ex < 0.0) {
+                                v = expand_avg(c, sxa, sya, Bq, wrap(iR, nx), j, xb - ex * h - centre(c->xf, nx, iR), dy);
+                            } else {
+                                real vL = expand_avg(c, sxa, sya, Bq, wrap(iL, nx), j, xb - centre(c->xf, nx, iL), dy);
+                                real vR = expand_avg(c, sxa, sya, Bq, wrap(iR, nx), j, xb - centre(c->xf, nx, iR), dy);
+                                v = 0.5 * (vL + vR);
+                            }
+                        }
+                    }
+                    fp[q * st] = v;
+                }
+                if (wallW) wall_face(c, WEST, fp, st, rho_cell[(long)j * nx]);
+                if (wallE) wall_face(c, EAST, fp, st, rho_cell[(long)j * nx + nx - 1]);
+            }
+        }
+    }
+
+    /* y-faces */
+    #pragma omp parallel for schedule(static)
+    for (int fj = 0; fj <= ny; fj++) {
+        double yb = c->yf[fj];
+        int wallS = (fj == 0 && !pery), wallN = (fj == ny && !pery);
+        for (int i = 0; i < nx; i++) {
+            double xc = centre(c->xf, nx, i), hx = 0.5 * width(c->xf, nx, i);
+            long fidx = (long)fj * nx + i;
+            for (int pt = 0; pt < npt; pt++) {
+                double xb = npt == 2 ? xc + (pt == 0 ? -g : g) * hx : xc;
+                real *fp = fy + (long)pt * nfy + fidx;
+                long st = (long)npt * nfy;
+                for (int q = 0; q < nq; q++) {
+                    const real *Bq = B + q * ncell;
+                    double ex = XI(c, q), ey = ETA(c, q);
+                    real v;
+                    if (c->recon == 2) {
+                        v = s2_value(c, Bq, 1, i, wrap(fj - 1, ny), i, wrap(fj, ny), ex, ey, h);
+                    } else {
+                        double dx = xb - ex * h - xc;
+                        if (wallS) {
+                            if (ey > 0.0) continue;
+                            v = expand_avg(c, sxa, sya, Bq, i, 0, dx, yb - ey * h - centre(c->yf, ny, 0));
+                        } else if (wallN) {
+                            if (ey < 0.0) continue;
+                            v = expand_avg(c, sxa, sya, Bq, i, ny - 1, dx, yb - ey * h - centre(c->yf, ny, ny - 1));
+                        } else {
+                            int jS = fj - 1, jN = fj;
+                            if (ey > 0.0) {
+                                v = expand_avg(c, sxa, sya, Bq, i, wrap(jS, ny), dx, yb - ey * h - centre(c->yf, ny, jS));
+                            } else if (ey < 0.0) {
+                                v = expand_avg(c, sxa, sya, Bq, i, wrap(jN, ny), dx, yb - ey * h - centre(c->yf, ny, jN));
+                            } else {
+                                real vS = expand_avg(c, sxa, sya, Bq, i, wrap(jS, ny), dx, yb - centre(c->yf, ny, jS));
+                                real vN = expand_avg(c, sxa, sya, Bq, i, wrap(jN, ny), dx, yb - centre(c->yf, ny, jN));
+                                v = 0.5 * (vS + vN);
+                            }
+                        }
+                    }
+                    fp[q * st] = v;
+                }
+                if (wallS) wall_face(c, SOUTH, fp, st, rho_cell[i]);
+                if (wallN) wall_face(c, NORTH, fp, st, rho_cell[(long)(ny - 1) * nx + i]);
+            }
+        }
+    }
+    free(sxa);
+    free(sya);
+}
+
+/* Micro-flux of the variants: recovery (eq. recover2f) at every face point, */
+/* then the face mean of the recovered values in eq. microflux.              */
+static int flux_points(const oc_case *c, const real *tau, const real *B, const real *rho_cell,
+                       double h, real *L)
+{
+    int nx = c->nx, ny = c->ny, nq = c->nq, npt = face_points(c);
+    long ncell = (long)nx * ny;
+    long nfx = (long)ny * (nx + 1), nfy = (long)(ny + 1) * nx;
+    int perx = c->bc[WEST] == BC_PERIODIC, pery = c->bc[SOUTH] == BC_PERIODIC;
+    if (c->recon == 2 && (!perx || !pery)) return -2;
+    real *fx = (real *)malloc(sizeof(real) * nq * npt * nfx);
+    real *fy = (real *)malloc(sizeof(real) * nq * npt * nfy);
+    if (!fx || !fy) { free(fx); free(fy); return -1; }
+
+    OC(face_point_values)(c, B, rho_cell, h, fx, fy);
+
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; j++)
+        for (int fi = 0; fi <= nx; fi++) {
+            real tb;
+            if (fi == 0 && !perx) tb = tau[(long)j * nx];
+            else if (fi == nx && !perx) tb = tau[(long)j * nx + nx - 1];
+            else tb = 0.5 * (tau[(long)j * nx + wrap(fi - 1, nx)] + tau[(long)j * nx + wrap(fi, nx)]);
+            for (int pt = 0; pt < npt; pt++)
+                recover_faces(c, fx, (long)npt * nfx, (long)pt * nfx + (long)j * (nx + 1) + fi, tb, h);
+        }
+    #pragma omp parallel for schedule(static)
+    for (int fj = 0; fj <= ny; fj++)
+        for (int i = 0; i < nx; i++) {
+            real tb;
+            if (fj == 0 && !pery) tb = tau[i];
+            else if (fj == ny && !pery) tb = tau[(long)(ny - 1) * nx + i];
+            else tb = 0.5 * (tau[(long)wrap(fj - 1, ny) * nx + i] + tau[(long)wrap(fj, ny) * nx + i]);
+            for (int pt = 0; pt < npt; pt++)
+                recover_faces(c, fy, (long)npt * nfy, (long)pt * nfy + (long)fj * nx + i, tb, h);
+        }
+
+    /* L_j = -(1/|V_j|) sum_faces (xi . n) |A| (mean over the face points of f_b) */
+    #pragma omp parallel for schedule(static)
+    for (int j = 0; j < ny; j++)
+        for (int i = 0; i < nx; i++) {
+            double dx = c->xf[i + 1] - c->xf[i];
+            double dy = c->yf[j + 1] - c->yf[j];
+            double vol = dx * dy;
+            for (int q = 0; q < nq; q++) {
+                real fw = 0, fe = 0, fs = 0, fn = 0;
+                for (int pt = 0; pt < npt; pt++) {
+                    const real *X = fx + ((long)q * npt + pt) * nfx;
+                    const real *Y = fy + ((long)q * npt + pt) * nfy;
+                    fw += X[(long)j * (nx + 1) + i] / npt;
+                    fe += X[(long)j * (nx + 1) + i + 1] / npt;
+                    fs += Y[(long)j * nx + i] / npt;
+                    fn += Y[(long)(j + 1) * nx + i] / npt;
+                }
+                real flux = XI(c, q) * dy * (fe - fw) + ETA(c, q) * dx * (fn - fs);
+                L[q * ncell + (long)j * nx + i] = -flux / vol;
+            }
+        }
+    free(fx);
+    free(fy);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Micro-flux L_j (eq. microflux, midpoint face rule, sign of R8) from the   */
 /* interface values: face moments -> E_b -> f_b (eq. recover2f) -> L.        */
 /* ------------------------------------------------------------------------ */
@@ -376,6 +716,7 @@ static void recover_faces(const oc_case *c, real *fb, long nf, long face,
 int OC(flux)(const oc_case *c, const real *tau, const real *B,
              const real *rho_cell, double h, real *L)
 {
+    if (c->recon != 0) return flux_points(c, tau, B, rho_cell, h, L);
     int nx = c->nx, ny = c->ny, nq = c->nq;
     long ncell = (long)nx * ny;
     long nfx = (long)ny * (nx + 1), nfy = (long)(ny + 1) * nx;
@@ -507,6 +848,156 @@ done:
     return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* A general member of the family of section "Time discretization": the    */
+/* free parameter a (1/3 <= a <= 1/2) with A = a/2 and K from              */
+/* A = (3K - 2)/(6K - 3); eq. EEWithP with the coefficients P_n, P' and    */
+/* P_{n+1} of eq. feqIntD3rd2 and the flux weights 3(2K-1)^2 and 1 over    */
+/* 4(3K^2 - 3K + 1).  State: fhat = f - P_{n+1} dt Omega.  The steps are    */
+/* those of the computational sequence with the family's times:            */
+/* t* = t_n + A dt (h1 = A dt), t' = t_n + a dt (T2 sub-step of a dt), and */
+/* t** = t_n + K dt (h2 = (K - a) dt).                                     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double A, K, Pn, Pp, Pn1, w1, w2;
+} family_coef;
+
+static family_coef family(double a)
+{
+    family_coef f;
+    f.A = 0.5 * a;
+    /* A = (3K - 2)/(6K - 3)  <=>  K = (2 - 3A)/(3 - 6A) */
+    f.K = (2.0 - 3.0 * f.A) / (3.0 - 6.0 * f.A);
+    f.Pn = (1.0 - 4.0 * a + 3.0 * a * a) / (6.0 * a * (a - 1.0));
+    f.Pp = -1.0 / (6.0 * a * (a - 1.0));
+    f.Pn1 = (-2.0 * a + 3.0 * a * a) / (6.0 * a * (a - 1.0));
+    double den = 4.0 * (3.0 * f.K * f.K - 3.0 * f.K + 1.0);
+    f.w1 = 3.0 * (2.0 * f.K - 1.0) * (2.0 * f.K - 1.0) / den;
+    f.w2 = 1.0 / den;
+    return f;
+}
+
+int OC(t3a_step)(const oc_case *c, const real *tau, const real *fhat, real *out)
+{
+    int nq = c->nq;
+    long n = (long)c->nx * c->ny;
+    double dt = c->dt, a = c->a_param;
+    family_coef fc = family(a);
+    size_t qs = sizeof(real) * nq * n, cs = sizeof(real) * n;
+    real *E = malloc(qs), *B = malloc(qs), *Ls = malloc(qs), *G = malloc(qs);
+    real *W = malloc(qs), *Bp = malloc(qs), *Lss = malloc(qs), *Ep = malloc(qs);
+    real *rho = malloc(cs), *ux = malloc(cs), *uy = malloc(cs);
+    real *rhop = malloc(cs), *uxp = malloc(cs), *uyp = malloc(cs);
+    int rc = 0;
+    if (!E || !B || !Ls || !G || !W || !Bp || !Lss || !Ep || !rho || !ux || !uy ||
+        !rhop || !uxp || !uyp) { rc = -1; goto done; }
+
+    OC(cell_moments)(c, fhat, rho, ux, uy);
+    OC(equilibrium)(c, rho, ux, uy, E);
+
+    /* Step 1: fbar^{+,h1} = f + (h1/2) Omega at t_n, from fhat = f - P_{n+1} dt Omega
+     * (both are E + kappa (f - E) with kappa = 1 - A D / 2 and 1 + P_{n+1} D) */
+    for (int q = 0; q < nq; q++)
+        for (long j = 0; j < n; j++) {
+            real t = tau[j];
+            B[q * n + j] = (t - 0.5 * fc.A * dt) / (t + fc.Pn1 * dt) * fhat[q * n + j] +
+                           (0.5 * fc.A + fc.Pn1) * dt / (t + fc.Pn1 * dt) * E[q * n + j];
+        }
+    if ((rc = OC(flux)(c, tau, B, rho, fc.A * dt, Ls))) goto done;
+
+    /* Step 2: T2 sub-step of a dt (Remark I): tilde f^+ = f + (a dt/2) Omega at
+     * t_n, tilde f(t') = tilde f^+ + a dt L(t*), then dt Omega(t') from
+     * tilde f = f - (a dt/2) Omega at t' */
+    for (int q = 0; q < nq; q++)
+        for (long j = 0; j < n; j++) {
+            real t = tau[j];
+            real ftp = (t - 0.5 * a * dt) / (t + fc.Pn1 * dt) * fhat[q * n + j] +
+                       (0.5 * a + fc.Pn1) * dt / (t + fc.Pn1 * dt) * E[q * n + j];
+            G[q * n + j] = ftp + a * dt * Ls[q * n + j];
+        }
+    OC(cell_moments)(c, G, rhop, uxp, uyp);
+    OC(equilibrium)(c, rhop, uxp, uyp, Ep);
+    for (int q = 0; q < nq; q++)
+        for (long j = 0; j < n; j++) {
+            real t = tau[j];
+            W[q * n + j] = -2.0 * dt / (2.0 * t + a * dt) * (G[q * n + j] - Ep[q * n + j]);
+        }
+
+    /* Step 3: fbar^{+,h2} = f + (h2/2) Omega at t' from tilde f, h2 = (K - a) dt */
+    for (int q = 0; q < nq; q++)
+        for (long j = 0; j < n; j++) {
+            real t = tau[j];
+            double h2 = (fc.K - a) * dt;
+            Bp[q * n + j] = (2.0 * t - h2) / (2.0 * t + a * dt) * G[q * n + j] +
+                            (h2 + a * dt) / (2.0 * t + a * dt) * Ep[q * n + j];
+        }
+    if ((rc = OC(flux)(c, tau, Bp, rhop, (fc.K - a) * dt, Lss))) goto done;
+
+    /* Step 4: eq. EEWithP: fhat^+ = ((tau - P_n dt) fhat + (P_n + P_{n+1}) dt E) /
+     * (tau + P_{n+1} dt), plus P' dt Omega(t') and the two fluxes */
+    for (int q = 0; q < nq; q++)
+        for (long j = 0; j < n; j++) {
+            long k = q * n + j;
+            real t = tau[j];
+            real fhp = (t - fc.Pn * dt) / (t + fc.Pn1 * dt) * fhat[k] +
+                       (fc.Pn + fc.Pn1) * dt / (t + fc.Pn1 * dt) * E[k];
+            out[k] = fhp + fc.Pp * W[k] + dt * (fc.w1 * Ls[k] + fc.w2 * Lss[k]);
+        }
+done:
+    free(E); free(B); free(Ls); free(G); free(W); free(Bp); free(Lss); free(Ep);
+    free(rho); free(ux); free(uy); free(rhop); free(uxp); free(uyp);
+    return rc;
+}
+
+int OC(t3a_run)(const oc_case *c, const real *tau, real *fhat, int nsteps)
+{
+    long m = (long)c->nq * c->nx * c->ny;
+    real *tmp = malloc(sizeof(real) * m);
+    if (!tmp) return -1;
+    for (int s = 0; s < nsteps; s++) {
+        int rc = OC(t3a_step)(c, tau, fhat, tmp);
+        if (rc) { free(tmp); return rc; }
+        memcpy(fhat, tmp, sizeof(real) * m);
+    }
+    free(tmp);
+    return 0;
+}
+
+/* fhat = f - P_{n+1} dt Omega(f) of the family member a, and its inverse */
+int OC(f_to_fhat_a)(const oc_case *c, const real *tau, const real *f, real *fhat)
+{
+    long n = (long)c->nx * c->ny;
+    double p1 = family(c->a_param).Pn1;
+    real *rho = malloc(sizeof(real) * n), *ux = malloc(sizeof(real) * n),
+         *uy = malloc(sizeof(real) * n);
+    if (!rho || !ux || !uy) { free(rho); free(ux); free(uy); return -1; }
+    OC(cell_moments)(c, f, rho, ux, uy);
+    for (int q = 0; q < c->nq; q++)
+        for (long j = 0; j < n; j++) {
+            real e = equilibrium_q(c, q, rho[j], ux[j], uy[j]);
+            fhat[q * n + j] = f[q * n + j] + p1 * c->dt / tau[j] * (f[q * n + j] - e);
+        }
+    free(rho); free(ux); free(uy);
+    return 0;
+}
+
+int OC(fhat_to_f_a)(const oc_case *c, const real *tau, const real *fhat, real *f)
+{
+    long n = (long)c->nx * c->ny;
+    double p1 = family(c->a_param).Pn1;
+    real *rho = malloc(sizeof(real) * n), *ux = malloc(sizeof(real) * n),
+         *uy = malloc(sizeof(real) * n);
+    if (!rho || !ux || !uy) { free(rho); free(ux); free(uy); return -1; }
+    OC(cell_moments)(c, fhat, rho, ux, uy);
+    for (int q = 0; q < c->nq; q++)
+        for (long j = 0; j < n; j++) {
+            real e = equilibrium_q(c, q, rho[j], ux[j], uy[j]);
+            f[q * n + j] = (tau[j] * fhat[q * n + j] + p1 * c->dt * e) / (tau[j] + p1 * c->dt);
+        }
+    free(rho); free(ux); free(uy);
+    return 0;
+}
+
 /* Stage-A product of one step (tilde f at t'), exposed for the tests. */
 int OC(t3s3_stage_a)(const oc_case *c, const real *tau, const real *fhat, real *G)
 {
@@ -603,6 +1094,24 @@ int OC(fhat_to_f)(const oc_case *c, const real *tau, const real *fhat, real *f)
         for (long j = 0; j < n; j++) {
             real e = equilibrium_q(c, q, rho[j], ux[j], uy[j]);
             f[q * n + j] = (4.0 * tau[j] * fhat[q * n + j] + c->dt * e) / (4.0 * tau[j] + c->dt);
+        }
+    free(rho); free(ux); free(uy);
+    return 0;
+}
+
+/* tilde f = f - (delta/2) Omega(f) of the T2 integrator with step delta, and */
+/* its inverse (Remark I)                                                    */
+int OC(f_to_ftilde)(const oc_case *c, const real *tau, double delta, const real *f, real *ft)
+{
+    long n = (long)c->nx * c->ny;
+    real *rho = malloc(sizeof(real) * n), *ux = malloc(sizeof(real) * n),
+         *uy = malloc(sizeof(real) * n);
+    if (!rho || !ux || !uy) { free(rho); free(ux); free(uy); return -1; }
+    OC(cell_moments)(c, f, rho, ux, uy);
+    for (int q = 0; q < c->nq; q++)
+        for (long j = 0; j < n; j++) {
+            real e = equilibrium_q(c, q, rho[j], ux[j], uy[j]);
+            ft[q * n + j] = f[q * n + j] + delta / (2.0 * tau[j]) * (f[q * n + j] - e);
         }
     free(rho); free(ux); free(uy);
     return 0;

@@ -43,6 +43,18 @@ struct dugks {
     bool prof_on = false;
     std::string variant;
     int device = 0;                      // device current at creation
+    // caller's device allocator (dugks_desc.dev_alloc / dev_free), or none
+    void *(*alloc_fn)(size_t, void *) = nullptr;
+    void (*free_fn)(void *, void *) = nullptr;
+    void *alloc_ctx = nullptr;
+    // variants (family member a, cell-average or S2 reconstruction): variant.hip
+    bool var = false;
+    VarArgs va{};
+    VarFamily vf{};
+    VarBuffers vb{};
+    // graph replay of single-handle steps (lattice kernels): [parity]
+    hipGraphExec_t step_exec[2] = {nullptr, nullptr};
+    int step_calls = 0;
     std::vector<double> hxi;             // host copy of the velocities, [2][nq]
     void *adj_ws = nullptr;              // dugks_backward workspace, kept between calls
     size_t adj_ws_bytes = 0;
@@ -95,10 +107,30 @@ static int fail(int code, const std::string &msg)
             return fail(DUGKS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-static int dalloc(dugks *h, void **p, size_t bytes)
+// device memory of the handle: the caller's allocator when it gave one
+static int dev_get(dugks *h, void **p, size_t bytes)
 {
+    if (h->alloc_fn) {
+        *p = h->alloc_fn(bytes ? bytes : 8, h->alloc_ctx);
+        if (!*p) return fail(DUGKS_ENOMEM, "dev_alloc returned NULL");
+        return DUGKS_OK;
+    }
     hipError_t e = hipMalloc(p, bytes ? bytes : 8);
     if (e != hipSuccess) return fail(DUGKS_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return DUGKS_OK;
+}
+
+static void dev_put(dugks *h, void *p)
+{
+    if (!p) return;
+    if (h->alloc_fn) h->free_fn(p, h->alloc_ctx);
+    else (void)hipFree(p);
+}
+
+static int dalloc(dugks *h, void **p, size_t bytes)
+{
+    int rc = dev_get(h, p, bytes);
+    if (rc) return rc;
     h->allocs.push_back(*p);
     return DUGKS_OK;
 }
@@ -380,11 +412,11 @@ int dugks_destroy(dugks_t *h)
         delete h->batch;
     }
     for (auto &e : h->ev) (void)hipEventDestroy(e);
-    if (h->adj_ws) {
-        (void)hipStreamSynchronize(h->stream);
-        (void)hipFree(h->adj_ws);
-    }
-    for (void *p : h->allocs) (void)hipFree(p);
+    for (auto &e : h->step_exec)
+        if (e) (void)hipGraphExecDestroy(e);
+    if (h->adj_ws || (h->alloc_fn && !h->allocs.empty())) (void)hipStreamSynchronize(h->stream);
+    dev_put(h, h->adj_ws);
+    for (void *p : h->allocs) dev_put(h, p);
     delete h;
     return DUGKS_OK;
 }
@@ -409,6 +441,16 @@ static int validate(const dugks_desc *d)
         return fail(DUGKS_EINVAL, "periodic sides must be paired");
     if (d->precision != DUGKS_FP64 && d->precision != DUGKS_FP32_DELTA)
         return fail(DUGKS_EINVAL, "unknown precision");
+    if (d->reconstruction < DUGKS_RECON_POINT || d->reconstruction > DUGKS_RECON_S2)
+        return fail(DUGKS_EINVAL, "unknown reconstruction");
+    if (d->family_a != 0.0 && !(d->family_a >= 1.0 / 3.0 && d->family_a <= 0.5))
+        return fail(DUGKS_EINVAL, "family_a must be 0 or lie in [1/3, 1/2]");
+    if (d->family_a != 0.0 && d->scheme == DUGKS_SCHEME_T2S3)
+        return fail(DUGKS_EINVAL, "family_a is a parameter of the third-order scheme");
+    if (!d->tau && !(d->tau0 > 0) && !(d->kn > 0 && d->l_ref > 0))
+        return fail(DUGKS_EINVAL, "no relaxation time: tau, tau0 > 0 or kn and l_ref > 0");
+    if ((d->dev_alloc == nullptr) != (d->dev_free == nullptr))
+        return fail(DUGKS_EINVAL, "dev_alloc and dev_free go together");
     // CFL: the characteristic foot point must stay within the upwind cell's stencil
     double cmax = 0;
     for (int q = 0; q < 2 * d->nq; q++) cmax = std::fmax(cmax, std::fabs(d->xi[q]));
@@ -440,12 +482,17 @@ static int check_tau(const double *tau, long long n, double tau0, double dt)
     return DUGKS_OK;
 }
 
-int dugks_create(const dugks_desc *d, dugks_t **out)
+int dugks_create(const dugks_desc *din, dugks_t **out)
 {
     if (!out) return fail(DUGKS_EINVAL, "null output handle");
     *out = nullptr;
-    int rc = validate(d);
+    int rc = validate(din);
     if (rc) return rc;
+    // relaxation time from the Knudsen number (paper, "Numerical tests":
+    // lambda = tau sqrt(pi RT / 2) and Kn = lambda / L)
+    dugks_desc dl = *din;
+    if (!dl.tau && !(dl.tau0 > 0)) dl.tau0 = dl.kn * dl.l_ref / std::sqrt(M_PI * dl.RT / 2.0);
+    const dugks_desc *d = &dl;
     const long long ncell = (long long)d->nx * d->ny;
     if ((rc = check_tau(d->tau, ncell, d->tau0, d->dt))) return rc;
     const int nq = d->nq;
@@ -486,6 +533,9 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     dugks *h = new dugks();
     h->stream = (hipStream_t)d->stream;
     h->hxi.assign(d->xi, d->xi + 2 * (size_t)nq);
+    h->alloc_fn = d->dev_alloc;
+    h->free_fn = d->dev_free;
+    h->alloc_ctx = d->alloc_ctx;
     h->delta = d->precision == DUGKS_FP32_DELTA;
     h->elem = h->delta ? 4 : 8;
     SweepParams &p = h->p;
@@ -493,6 +543,10 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     p.ny = d->ny;
     p.ncell = ncell;
     p.t2 = d->scheme == DUGKS_SCHEME_T2S3;
+    // variants of the method run the kernels of variant.hip
+    const double fam_a = d->family_a != 0.0 ? d->family_a : 1.0 / 3.0;
+    h->var = fam_a != 1.0 / 3.0 || d->reconstruction != DUGKS_RECON_POINT;
+    p.state_m = p.t2 ? 2.0 : (h->var ? 1.0 / var_family(fam_a, d->dt).Pn1 : 4.0);
     p.perx = d->bc[0] == DUGKS_BC_PERIODIC;
     p.pery = d->bc[2] == DUGKS_BC_PERIODIC;
     p.nq = nq;
@@ -658,6 +712,10 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
     // grid
     const bool unif = is_uniform(d->xf, d->nx) && is_uniform(d->yf, d->ny);
     p.uniform = unif;
+    if (h->var && (!unif || h->delta || !p.perx || !p.pery)) {
+        delete h;
+        return fail(DUGKS_ENOTSUP, "the scheme and reconstruction variants run FP64 on uniform periodic grids");
+    }
     p.inv_dx = 1.0 / (d->xf[1] - d->xf[0]);
     p.inv_dy = 1.0 / (d->yf[1] - d->yf[0]);
     std::vector<double> dxl, dxr, sxd1, sxd2, ixd, dyl, dyr, syd1, syd2, iyd;
@@ -842,12 +900,49 @@ int dugks_create(const dugks_desc *d, dugks_t **out)
         h->face_mom = (double *)fm;
         h->cell_part = (double *)cp;
     }
+    if (h->var) {
+        const int npt = d->reconstruction == DUGKS_RECON_CELL_AVERAGE ? 2 : 1;
+        const size_t qn = sizeof(double) * (size_t)nq * ncell;
+        void *vB, *vG, *vL, *vM0, *vM1, *vFx, *vFy;
+        if ((rc = dalloc(h, &vB, qn)) || (rc = dalloc(h, &vG, qn)) || (rc = dalloc(h, &vL, qn)) ||
+            (rc = dalloc(h, &vM0, 3 * sizeof(double) * ncell)) || (rc = dalloc(h, &vM1, 3 * sizeof(double) * ncell)) ||
+            (rc = dalloc(h, &vFx, npt * qn)) || (rc = dalloc(h, &vFy, npt * qn))) {
+            dugks_destroy(h);
+            return rc;
+        }
+        h->vb = VarBuffers{(double *)vB, (double *)vG, (double *)vL, (double *)vM0, (double *)vM1, (double *)vFx,
+                           (double *)vFy};
+        VarArgs &a = h->va;
+        a.nx = d->nx;
+        a.ny = d->ny;
+        a.nq = nq;
+        a.n = ncell;
+        a.dx = d->xf[1] - d->xf[0];
+        a.dy = d->yf[1] - d->yf[0];
+        a.RT = d->RT;
+        a.xi = p.xi;
+        a.eta = p.eta;
+        a.w = p.w;
+        a.tau = p.tau_field ? p.tau : nullptr;
+        a.tau0 = p.tau0;
+        a.recon = d->reconstruction;
+        a.kappa = p.kappa;
+        h->vf = var_family(fam_a, d->dt);
+    }
     void *bad = nullptr;
     if ((rc = dalloc(h, &bad, sizeof(int)))) { dugks_destroy(h); return rc; }
     h->d_bad = (int *)bad;
+    p.bad = h->d_bad;
+    h->va.bad = h->d_bad;
     HIPCHECK(hipMemset(h->d_bad, 0, sizeof(int)));
-    char buf[128];
-    if (h->lat)
+    char buf[160];
+    if (h->var)
+        snprintf(buf, sizeof buf, "variant %s a=%.6g reconstruction %s, Q=%d fp64 (variant.hip)",
+                 p.t2 ? "T2" : "T3 family", fam_a,
+                 d->reconstruction == DUGKS_RECON_POINT ? "point/midpoint"
+                 : d->reconstruction == DUGKS_RECON_CELL_AVERAGE ? "cell-average/two-point Gauss" : "S2",
+                 nq);
+    else if (h->lat)
         snprintf(buf, sizeof buf, "lattice D2Q%d %s tile %dx%d %s", h->lat, h->delta ? "fp32-delta" : "fp64",
                  lx, ly, unif ? "uniform" : "non-uniform");
     else
@@ -951,44 +1046,102 @@ static int lq_stage(dugks *h, const LQStage &a)
 
 static int batch_step(dugks_t *h, int nsteps);
 
+// One step of a single handle on its own stream (lattice, any-size or
+// variant kernels); with timing on, each stage (or kernel) gets its events.
+static int step_once(dugks *h)
+{
+    void *X = h->state[h->cur], *Y = h->state[1 - h->cur];
+    int rc;
+    const bool whole = h->lat || h->var || !h->prof_on;   // stage records (else per-kernel ones)
+    if (h->var) {
+        if (whole && (rc = record(h, KC_STAGE_A, true))) return rc;
+        HIPCHECK(variant_step(h->va, h->vf, h->p.t2 != 0, (const double *)X, (double *)Y, h->vb, h->stream));
+        if (whole && (rc = record(h, KC_STAGE_A, false))) return rc;
+        return DUGKS_OK;
+    }
+    if (h->p.t2) {
+        // T2S3: one stage-A-shaped sweep from ftilde(t_n) to ftilde(t_n + dt)
+        if (whole && (rc = record(h, KC_STAGE_A, true))) return rc;
+        if (h->lat) {
+            HIPCHECK(lattice_stage(h, 0, X, nullptr, Y));
+        } else {
+            if ((rc = lq_stage(h, lq_args(h, 0, X, nullptr, Y)))) return rc;
+            // the cell reduction wrote the moments of Y into the stage-output slot
+            std::swap(h->mom_state, h->mom_G);
+        }
+        if (whole && (rc = record(h, KC_STAGE_A, false))) return rc;
+        return DUGKS_OK;
+    }
+    if (whole && (rc = record(h, KC_STAGE_A, true))) return rc;
+    if (h->lat) {
+        HIPCHECK(lattice_stage(h, 0, X, nullptr, h->G));
+    } else {
+        if ((rc = lq_stage(h, lq_args(h, 0, X, nullptr, h->G)))) return rc;
+    }
+    if (whole && (rc = record(h, KC_STAGE_A, false))) return rc;
+    if (whole && (rc = record(h, KC_STAGE_C, true))) return rc;
+    if (h->lat) {
+        HIPCHECK(lattice_stage(h, 1, h->G, X, Y));
+    } else {
+        // the moments of fhat(t_n) are read by the update and overwritten by
+        // the cell reduction that follows it on the same stream
+        if ((rc = lq_stage(h, lq_args(h, 1, h->G, X, Y)))) return rc;
+    }
+    if (whole && (rc = record(h, KC_STAGE_C, false))) return rc;
+    return DUGKS_OK;
+}
+
+// HIP graph of one step of a lattice handle from state[par] to state[1 - par]
+static int step_graph(dugks *h, int par)
+{
+    if (h->step_exec[par]) return DUGKS_OK;
+    hipStream_t s = h->stream;
+    bool own = false;
+    if (!s) {   // stream capture needs a real stream
+        HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        own = true;
+    }
+    hipStream_t keep = h->stream;
+    const int keep_cur = h->cur;
+    h->stream = s;
+    h->cur = par;
+    HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = step_once(h);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    h->stream = keep;
+    h->cur = keep_cur;
+    if (own) (void)hipStreamDestroy(s);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(DUGKS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->step_exec[par], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        h->step_exec[par] = nullptr;
+        return fail(DUGKS_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    }
+    return DUGKS_OK;
+}
+
 int dugks_step(dugks_t *h, int nsteps)
 {
     if (!h || nsteps < 0) return fail(DUGKS_EINVAL, "bad arguments");
     if (h->batch) return batch_step(h, nsteps);
+    // lattice handles replay a captured step from the second call on (not
+    // while kernel timing is on: the events go between the launches)
+    const bool graph = h->lat && !h->var && !h->prof_on && h->step_calls > 0;
+    if (nsteps > 0) h->step_calls++;
+    int rc;
     for (int s = 0; s < nsteps; s++) {
-        void *X = h->state[h->cur], *Y = h->state[1 - h->cur];
-        int rc;
-        const bool whole = h->lat || !h->prof_on;   // stage records (else per-kernel ones)
-        if (h->p.t2) {
-            // T2S3: one stage-A-shaped sweep from ftilde(t_n) to ftilde(t_n + dt)
-            if (whole && (rc = record(h, KC_STAGE_A, true))) return rc;
-            if (h->lat) {
-                HIPCHECK(lattice_stage(h, 0, X, nullptr, Y));
-            } else {
-                if ((rc = lq_stage(h, lq_args(h, 0, X, nullptr, Y)))) return rc;
-                // the cell reduction wrote the moments of Y into the stage-output slot
-                std::swap(h->mom_state, h->mom_G);
-            }
-            if (whole && (rc = record(h, KC_STAGE_A, false))) return rc;
-            h->cur = 1 - h->cur;
-            continue;
+        if (graph) {
+            if ((rc = step_graph(h, h->cur))) return rc;
+            HIPCHECK(hipGraphLaunch(h->step_exec[h->cur], h->stream));
+        } else if ((rc = step_once(h))) {
+            return rc;
         }
-        if (whole && (rc = record(h, KC_STAGE_A, true))) return rc;
-        if (h->lat) {
-            HIPCHECK(lattice_stage(h, 0, X, nullptr, h->G));
-        } else {
-            if ((rc = lq_stage(h, lq_args(h, 0, X, nullptr, h->G)))) return rc;
-        }
-        if (whole && (rc = record(h, KC_STAGE_A, false))) return rc;
-        if (whole && (rc = record(h, KC_STAGE_C, true))) return rc;
-        if (h->lat) {
-            HIPCHECK(lattice_stage(h, 1, h->G, X, Y));
-        } else {
-            // the moments of fhat(t_n) are read by the update and overwritten by
-            // the cell reduction that follows it on the same stream
-            if ((rc = lq_stage(h, lq_args(h, 1, h->G, X, Y)))) return rc;
-        }
-        if (whole && (rc = record(h, KC_STAGE_C, false))) return rc;
         h->cur = 1 - h->cur;
     }
     return DUGKS_OK;
@@ -1076,13 +1229,15 @@ int dugks_sync(dugks_t *h)
         }
         return DUGKS_OK;
     }
-    HIPCHECK(hipMemsetAsync(h->d_bad, 0, sizeof(int), h->stream));
-    HIPCHECK(launch_moments(h->p, h->delta, h->state[h->cur], nullptr, nullptr, nullptr, h->d_bad,
-                            h->stream));
+    // the stage kernels raise the flag when they write a non-finite value
     int bad = 0;
     HIPCHECK(hipMemcpyAsync(&bad, h->d_bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHECK(hipStreamSynchronize(h->stream));
-    if (bad) return fail(DUGKS_ENONFINITE, "non-finite density in the state");
+    if (bad) {
+        HIPCHECK(hipMemsetAsync(h->d_bad, 0, sizeof(int), h->stream));
+        HIPCHECK(hipStreamSynchronize(h->stream));
+        return fail(DUGKS_ENONFINITE, "non-finite value written by a stage since the last sync");
+    }
     return DUGKS_OK;
 }
 
@@ -1149,6 +1304,9 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
         if (descs[k].precision != descs[0].precision || descs[k].stream != descs[0].stream)
             return fail(DUGKS_EINVAL, "instances of a batch share precision and stream");
         if (descs[k].scheme != DUGKS_SCHEME_T3S3) return fail(DUGKS_EINVAL, "batches run the T3S3 scheme");
+        if ((descs[k].family_a != 0.0 && descs[k].family_a != 1.0 / 3.0) ||
+            descs[k].reconstruction != DUGKS_RECON_POINT)
+            return fail(DUGKS_EINVAL, "batches run the T3S3 scheme with the default reconstruction");
     }
     dugks *h = new dugks();
     h->stream = (hipStream_t)descs[0].stream;
@@ -1447,7 +1605,7 @@ static int backward_check(dugks *h, int nsteps, int ckpt_every)
 {
     if (nsteps < 0 || ckpt_every < 1) return fail(DUGKS_EINVAL, "bad arguments");
     if (h->batch) return fail(DUGKS_ENOTSUP, "backward of a batch handle");
-    if (h->p.t2) return fail(DUGKS_ENOTSUP, "the adjoint is written for the T3S3 scheme");
+    if (h->p.t2 || h->var) return fail(DUGKS_ENOTSUP, "the adjoint is written for the T3S3 scheme");
     if (!h->p.perx || !h->p.pery || !h->p.uniform)
         return fail(DUGKS_ENOTSUP, "the adjoint supports periodic uniform grids only");
     return DUGKS_OK;
@@ -1581,13 +1739,12 @@ int dugks_backward(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
     const size_t need = backward_bytes(h, nsteps, ckpt_every);
     if (need > h->adj_ws_bytes) {
         HIPCHECK(hipStreamSynchronize(h->stream));
-        if (h->adj_ws) (void)hipFree(h->adj_ws);
+        dev_put(h, h->adj_ws);
         h->adj_ws = nullptr;
         h->adj_ws_bytes = 0;
-        hipError_t e = hipMalloc(&h->adj_ws, need);
-        if (e != hipSuccess) {
+        if ((rc = dev_get(h, &h->adj_ws, need))) {
             h->adj_ws = nullptr;
-            return fail(DUGKS_ENOMEM, std::string("adjoint workspace: ") + hipGetErrorString(e));
+            return rc;
         }
         h->adj_ws_bytes = need;
     }

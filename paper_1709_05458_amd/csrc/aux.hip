@@ -52,8 +52,9 @@ __device__ void cell_moments(const SweepParams &p, const S *x, long long cell, d
 }
 
 // The stored state is f - (dt/m) Omega(f) = f + dt/(m tau) (f - E): m = 4 for
-// T3S3 (fhat, eq. feqIntD3rdHat2 definitions), 2 for T2S3 (ftilde, Remark I).
-__device__ __forceinline__ double state_m(const SweepParams &p) { return p.t2 ? 2.0 : 4.0; }
+// T3S3 (fhat, eq. feqIntD3rdHat2 definitions), 2 for the T2 step (ftilde,
+// Remark I), 1/P_{n+1} for the member a of the family (eq. EEWithP).
+__device__ __forceinline__ double state_m(const SweepParams &p) { return p.state_m; }
 
 template <class S, bool DELTA>
 __global__ void k_set_state(const SweepParams p, const double *__restrict__ f, S *__restrict__ x)

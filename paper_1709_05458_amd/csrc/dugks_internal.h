@@ -72,6 +72,7 @@ struct SweepParams {
     int tau_field;
     UniformCoef uc;
     double iRT;              // 1 / RT
+    double state_m;          // stored state f + dt/(state_m tau) (f - E): 4 (T3S3), 2 (T2), 1/P_{n+1} (family a)
     Geometry g;
     // velocity set (device)
     const double *xi, *eta, *w;
@@ -100,6 +101,7 @@ struct SweepParams {
     // lq_update's own split of q (its work items are 256 cells x lq_uchunk velocities)
     int lq_uchunk, lq_nuchunk;
     const void *lq_rec;      // [nq] QRec<float> (FP32-delta) or QRec<double> (FP64)
+    int *bad;                // set to 1 by a stage kernel that writes a non-finite value
 };
 
 // Per-stage arguments of the large-velocity-set kernels.
@@ -141,6 +143,51 @@ struct StageIO {
     const void *coef;   // fast-path face weights of the stage
     double h;           // characteristic step of the stage
 };
+
+// Interface reconstructions (dugks_desc.reconstruction).
+enum { RECON_POINT = 0, RECON_CELL_AVERAGE = 1, RECON_S2 = 2 };
+
+// Arguments of the variant kernels (variant.hip): uniform periodic grids, FP64.
+struct VarArgs {
+    int nx, ny, nq;
+    long long n;
+    double dx, dy, RT;
+    const double *xi, *eta, *w;
+    const double *tau;   // [cell] or nullptr for tau0
+    double tau0;
+    int recon;
+    double kappa;        // coefficient of the quadratic expansion term
+    int *bad;            // non-finite flag of the handle
+};
+
+// The member a of the time-discretization family: A = a/2, K from
+// A = (3K-2)/(6K-3), P_n, P', P_{n+1} and the flux weights w1, w2.
+struct VarFamily {
+    double dt, a, A, K, Pn, Pp, Pn1, w1, w2;
+};
+__host__ __device__ inline VarFamily var_family(double a, double dt)
+{
+    VarFamily f;
+    f.dt = dt;
+    f.a = a;
+    f.A = 0.5 * a;
+    f.K = (2.0 - 3.0 * f.A) / (3.0 - 6.0 * f.A);
+    f.Pn = (1.0 - 4.0 * a + 3.0 * a * a) / (6.0 * a * (a - 1.0));
+    f.Pp = -1.0 / (6.0 * a * (a - 1.0));
+    f.Pn1 = (-2.0 * a + 3.0 * a * a) / (6.0 * a * (a - 1.0));
+    const double den = 4.0 * (3.0 * f.K * f.K - 3.0 * f.K + 1.0);
+    f.w1 = 3.0 * (2.0 * f.K - 1.0) * (2.0 * f.K - 1.0) / den;
+    f.w2 = 1.0 / den;
+    return f;
+}
+
+// Work arrays of a variant step (device): B, G, L* ([q][cell]), moments
+// M0, M1 ([3][cell]) and the face-point values Fx, Fy ([q][point][cell]).
+struct VarBuffers {
+    double *B, *G, *Ls, *M0, *M1, *Fx, *Fy;
+};
+hipError_t variant_step(const VarArgs &a, const VarFamily &fam, bool t2, const double *X, double *Y,
+                        const VarBuffers &b, hipStream_t s);
 
 // Kernel classes for event timing.
 enum KernelClass { KC_STAGE_A = 0, KC_STAGE_C = 1, KC_AUX = 2, KC_LQ_FACES = 3, KC_LQ_UPDATE = 4, KC_ADJ_STEP = 5,

@@ -533,6 +533,8 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
              }
              const S Rq = GENERAL ? out[q * n + ocell] : t.R[q];
              out[q * n + ocell] = fmaS(aL, L, Rq);
+             // non-finite flag, tested on one velocity (see dugks_sync)
+             if (q == 0 && !__builtin_isfinite(out[q * n + ocell])) *p.bad = 1;
          }()),
          ...);
     }(Seq{});

@@ -379,7 +379,11 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
     // and odd (linear and cubic) parts
     auto store = [&](int q, S M, S wq) {
         const S r = R0[q];
-        *(S *)((char *)(out + (size_t)q * no) + (unsigned)(sizeof(S) * oc)) = DELTA ? r + M : fmaS(wq, M, r);
+        const S v = DELTA ? r + M : fmaS(wq, M, r);
+        *(S *)((char *)(out + (size_t)q * no) + (unsigned)(sizeof(S) * oc)) = v;
+        // a non-finite value anywhere in the cell's neighbourhood reaches
+        // every velocity through the moments, so one velocity is tested
+        if (q == 0 && !__builtin_isfinite(v)) *p.bad = 1;
     };
     [&]<int... qs>(std::integer_sequence<int, qs...>) {
         (([&] {

@@ -760,6 +760,8 @@ __device__ void lq_update_body(const SweepParams &p, const LQStage &a, int block
             if (a.stage != 0) R = fmaS(kf_own, fo[u], R);
             const S y = fmaS(aL, La, fmaS(sq, Mq, R));
             if (valid) out[(size_t)q * n + cell] = y;
+            // non-finite flag, tested on the first velocity of the chunk (see dugks_sync)
+            if (valid && q == q0 && !__builtin_isfinite(y)) *p.bad = 1;
             const double *w3 = rq.wm;
             const double yd = (double)y;
             m0 = __builtin_fma(w3[0], yd, m0);

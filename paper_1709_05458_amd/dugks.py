@@ -17,6 +17,10 @@ LIB_PATH = os.path.join(HERE, "libdugks.so")
 
 FP64, FP32_DELTA = 0, 1
 T3S3, T2S3 = 0, 1   # time integrators (dugks_scheme)
+RECON_POINT, RECON_CELL_AVERAGE, RECON_S2 = 0, 1, 2   # interface reconstructions (dugks_reconstruction)
+# device allocator callbacks of dugks_desc: void *(size_t bytes, void *ctx), void (void *ptr, void *ctx)
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
 MEM_HOST, MEM_DEVICE = 0, 1
 ALLOW_MOMENT_DEFECT = 1
 FORCE_GENERIC = 2
@@ -43,7 +47,10 @@ class DugksDesc(ctypes.Structure):
                 ("precision", c_int), ("rho0", c_double), ("taylor_quad", c_double),
                 ("stream", c_void_p), ("flags", c_int),
                 ("tile_x", c_int), ("tile_y", c_int),
-                ("scheme", c_int)]
+                ("scheme", c_int),
+                ("kn", c_double), ("l_ref", c_double),
+                ("family_a", c_double), ("reconstruction", c_int),
+                ("dev_alloc", c_void_p), ("dev_free", c_void_p), ("alloc_ctx", c_void_p)]
 
 
 _lib = None
@@ -124,8 +131,11 @@ def _default_stream():
 
 
 def make_desc(case, precision=FP64, taylor_quad=1.0, stream=None, tile=None, allow_defect=False,
-              tau=None, force_generic=False, d=None, scheme=T3S3):
-    """Fill a DugksDesc from a cases.Case; returns (desc, arrays to keep alive)."""
+              tau=None, force_generic=False, d=None, scheme=T3S3, tau_field=False, family_a=0.0,
+              reconstruction=RECON_POINT, kn=None, allocator=None):
+    """Fill a DugksDesc from a cases.Case; returns (desc, arrays to keep alive).
+    kn = (Kn, L_ref) leaves tau to the library (tau0 = Kn L_ref / sqrt(pi RT / 2));
+    allocator = (dev_alloc, dev_free) as ALLOC_FN / FREE_FN callbacks."""
     g, vs = case.grid, case.vs
     keep = [np.ascontiguousarray(g.xf, dtype=np.float64),
             np.ascontiguousarray(g.yf, dtype=np.float64),
@@ -138,11 +148,15 @@ def make_desc(case, precision=FP64, taylor_quad=1.0, stream=None, tile=None, all
     d.RT, d.dt = vs.RT, case.dt
     tau = case.tau if tau is None else tau
     tau = np.asarray(tau, dtype=np.float64)
-    if tau.ndim == 0 or np.ptp(tau) == 0.0:
+    if kn is not None:
+        d.tau = POINTER(c_double)()
+        d.tau0 = 0.0
+        d.kn, d.l_ref = float(kn[0]), float(kn[1])
+    elif not tau_field and (tau.ndim == 0 or np.ptp(tau) == 0.0):
         d.tau = POINTER(c_double)()
         d.tau0 = float(tau.reshape(-1)[0])
     else:
-        t = np.ascontiguousarray(tau.reshape(-1))
+        t = np.ascontiguousarray(np.broadcast_to(tau, (g.ny, g.nx)).reshape(-1))
         keep.append(t)
         d.tau = _dptr(t)
         d.tau0 = float(t.mean())
@@ -159,6 +173,12 @@ def make_desc(case, precision=FP64, taylor_quad=1.0, stream=None, tile=None, all
     if tile:
         d.tile_x, d.tile_y = tile
     d.scheme = scheme
+    d.family_a = float(family_a)
+    d.reconstruction = int(reconstruction)
+    if allocator is not None:
+        keep.extend(allocator)
+        d.dev_alloc = ctypes.cast(allocator[0], c_void_p)
+        d.dev_free = ctypes.cast(allocator[1], c_void_p)
     return d, keep
 
 
@@ -167,7 +187,8 @@ class Solver:
 
     def __init__(self, case, precision: int = FP64, taylor_quad: float = 1.0, stream=None,
                  tile=None, allow_defect: bool = False, tau=None, force_generic: bool = False,
-                 tau_field: bool = False, scheme: int = T3S3, _borrowed=None):
+                 tau_field: bool = False, scheme: int = T3S3, family_a: float = 0.0,
+                 reconstruction: int = RECON_POINT, kn=None, allocator=None, _borrowed=None):
         g, vs = case.grid, case.vs
         self.case = case
         self.nx, self.ny, self.nq = g.nx, g.ny, vs.nq
@@ -177,51 +198,14 @@ class Solver:
         if _borrowed is not None:
             self.h = _borrowed
             return
-        self._keep = [np.ascontiguousarray(g.xf, dtype=np.float64),
-                      np.ascontiguousarray(g.yf, dtype=np.float64),
-                      np.ascontiguousarray(vs.xi.reshape(-1), dtype=np.float64),
-                      np.ascontiguousarray(vs.w, dtype=np.float64)]
-        d = DugksDesc()
-        d.nx, d.ny, d.nq = g.nx, g.ny, vs.nq
-        d.xf, d.yf = _dptr(self._keep[0]), _dptr(self._keep[1])
-        d.xi, d.w = _dptr(self._keep[2]), _dptr(self._keep[3])
-        d.RT, d.dt = vs.RT, case.dt
-        tau = case.tau if tau is None else tau
-        tau = np.asarray(tau, dtype=np.float64)
-        if not tau_field and (tau.ndim == 0 or np.ptp(tau) == 0.0):
-            d.tau = POINTER(c_double)()
-            d.tau0 = float(tau.reshape(-1)[0])
-            self.tau_field = False
-        else:
-            t = np.ascontiguousarray(np.broadcast_to(tau, (g.ny, g.nx)).reshape(-1))
-            self._keep.append(t)
-            d.tau = _dptr(t)
-            d.tau0 = float(t.mean())
-            self.tau_field = True
-        for k in range(4):
-            d.bc[k] = int(case.bc[k])
-            d.u_wall[k][0] = float(case.u_wall[k][0])
-            d.u_wall[k][1] = float(case.u_wall[k][1])
-        d.precision = precision
-        d.rho0 = float(case.rho0)
-        d.taylor_quad = taylor_quad
-        if stream is None:
-            try:
-                import torch
-                if torch.cuda.is_available():
-                    stream = torch.cuda.current_stream().cuda_stream
-            except Exception:
-                stream = None
-        d.stream = c_void_p(stream) if stream else None
-        d.flags = (ALLOW_MOMENT_DEFECT if allow_defect else 0) | (FORCE_GENERIC if force_generic else 0)
-        if tile:
-            d.tile_x, d.tile_y = tile
-        d.scheme = scheme
+        d, self._keep = make_desc(case, precision, taylor_quad, stream, tile, allow_defect, tau, force_generic,
+                                  scheme=scheme, tau_field=tau_field, family_a=family_a,
+                                  reconstruction=reconstruction, kn=kn, allocator=allocator)
+        self.tau_field = bool(d.tau)
         self.desc = d
         h = c_void_p()
         check(lib().dugks_create(byref(d), byref(h)), "dugks_create")
         self.h = h
-        self.precision = precision
 
     # -- lifetime ------------------------------------------------------------
     def close(self):
@@ -448,27 +432,6 @@ class BatchSolver:
 
     def sync(self):
         check(lib().dugks_sync(self.h), "dugks_sync")
-
-    def run_until_steady(self, tol: float = 1e-6, every: int = 1000, max_steps: int = 1_000_000):
-        """Step until the paper's steady-state criterion holds (cavity section):
-        sqrt(sum |u^(n+every) - u^(n)|^2) / sqrt(sum |u^(n+every)|^2) <= tol,
-        checked every `every` steps.  Returns (steps taken, last residual); the
-        residual is None if fewer than two checks ran.  Raises DugksError on a
-        non-finite state."""
-        _, ux, uy = self.moments()
-        done, res = 0, None
-        while done < max_steps:
-            n = min(every, max_steps - done)
-            self.step(n)
-            done += n
-            self.sync()
-            _, vx, vy = self.moments()
-            den = float(np.sqrt((vx * vx + vy * vy).sum()))
-            res = float(np.sqrt(((vx - ux) ** 2 + (vy - uy) ** 2).sum())) / den if den > 0 else 0.0
-            ux, uy = vx, vy
-            if n == every and res <= tol:
-                break
-        return done, res
 
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(256)

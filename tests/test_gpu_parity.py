@@ -213,16 +213,24 @@ def test_set_state_get_state_round_trip():
     s.close()
 
 
-def test_nonfinite_state_is_reported():
-    case = _mk("tgv32_d2q9")
-    s = dugks.Solver(case, dugks.FP64)
+@pytest.mark.parametrize("name,prec", [("tgv32_d2q9", "FP64"), ("tgv32_d2q9", "FP32_DELTA"),
+                                       ("cavity_bb_33x30", "FP64"), ("nc8_ds_tanh", "FP64")])
+def test_nonfinite_state_is_reported(name, prec):
+    # the stage kernels raise the handle's flag when they write a non-finite
+    # value; dugks_sync reports it and clears it
+    case = _mk(name)
+    s = dugks.Solver(case, getattr(dugks, prec), allow_defect=True)
     s.init_equilibrium(case.rho, case.ux, case.uy)
+    s.step(2)
+    s.sync()   # finite: no report
     f = s.get_state()
     f[0, 3, 3] = np.nan
     s.set_state(f)
+    s.step(1)
     with pytest.raises(dugks.DugksError) as e:
         s.sync()
     assert e.value.code == -6
+    s.sync()   # the report cleared the flag; no stage ran since
     s.close()
 
 

@@ -1,9 +1,12 @@
 """The paper's convergence table (Taylor vortex flow section, dt/tau = 4,
 dt = 1e-5, nu = 0.01, domain [0,1]^2, A = B = 2 pi, u0 = 1, E(u) at t = 1 s,
-i.e. 1e5 steps) run in FP64 on the GPU for both readings of the quadratic
-term of the interface expansion.  The run is too long for the CPU oracle
-beyond N = 64; the GPU path is tied to the oracle element by element
-elsewhere, and here also on the first 200 steps at N = 32.
+i.e. 1e5 steps) run in FP64 on the GPU: the T3S3 rows for both readings of
+the quadratic term of the interface expansion, the T2S2 rows (the paper's
+comparison scheme, S2 reconstruction), the cell-average / two-point Gauss
+reading and other members of the time-discretization family.  The run is
+too long for the CPU oracle beyond N = 64; the GPU paths are tied to the
+oracle element by element elsewhere, and here also on the first 200 steps
+at N = 32.
 
 Golden values: tests/golden/table1_t3s3.txt (the paper's table).
 """
@@ -44,15 +47,48 @@ def _case(N):
                   {"u0": 1.0, "A": A, "B": B, "nu": NU})
 
 
-def _error(case, ux, uy, t):
+def _error(case, ux, uy, t, avg=False):
+    if avg:
+        return _error_avg(case, ux, uy, t)
     g = case.grid
     _, uxa, uya = C.taylor_green_fields(g.xc, g.yc, t, 1.0, 2 * math.pi, 2 * math.pi, NU, case.vs.RT)
     return math.sqrt(((ux - uxa) ** 2 + (uy - uya) ** 2).sum() / (uxa ** 2 + uya ** 2).sum())
 
 
-def _paper():
+def _paper(model="T3S3"):
     rows = [l.split() for l in open(GOLD) if l.strip() and not l.startswith("#")]
-    return {int(n): float(e) for m, n, e in rows if m == "T3S3"}
+    return {int(n): float(e) for m, n, e in rows if m == model}
+
+
+def _table(Ns, avg=False, **kw):
+    """E(u) at t = 1 for each N (FP64; kw: Solver options of the variant)."""
+    steps = int(round(T / DT))
+    res = {}
+    for N in Ns:
+        case = _case(N)
+        s = dugks.Solver(case, dugks.FP64, **kw)
+        s.set_state(oracle.chapman_enskog_tgv(case, cell_average=avg))
+        s.step(steps)
+        s.sync()
+        _, ux, uy = s.moments()
+        res[N] = _error(case, ux, uy, steps * DT, avg)
+        s.close()
+    return res
+
+
+def _orders(res):
+    Ns = sorted(res)
+    return [math.log(res[a] / res[b]) / math.log(b / a) for a, b in zip(Ns, Ns[1:])]
+
+
+def _error_avg(case, ux, uy, t):
+    # against the cell averages of the analytic field (cell-average reading)
+    g = case.grid
+    _, uxa, uya = C.taylor_green_fields(g.xc, g.yc, t, 1.0, 2 * math.pi, 2 * math.pi, NU, case.vs.RT)
+    h = 0.5 * (g.xf[1] - g.xf[0])
+    f = np.sinc(2 * math.pi * h / math.pi) ** 2
+    uxa, uya = uxa * f, uya * f
+    return math.sqrt(((ux - uxa) ** 2 + (uy - uya) ** 2).sum() / (uxa ** 2 + uya ** 2).sum())
 
 
 def test_gpu_matches_oracle_on_the_table_setup():
@@ -76,25 +112,79 @@ def test_gpu_matches_oracle_on_the_table_setup():
 
 
 def test_convergence_table():
+    # The printed expansion (reading R3, the default) against the paper's
+    # T3S3 row: at or below it everywhere; on the three finest grids within
+    # 15% of it (measured -12%, -8%, -7%) and the last order within 0.2 of
+    # the paper's 3.05.  At N = 32 it is 6.5 times below the paper's value, so
+    # the paper's 32 -> 64 order of 4.1 is not reproduced (measured 2.26).
     paper = _paper()
-    steps = int(round(T / DT))
-    res = {}
-    for kappa in (1.0, 0.5):
-        for N in sorted(paper):
-            case = _case(N)
-            s = dugks.Solver(case, dugks.FP64, taylor_quad=kappa)
-            s.set_state(oracle.chapman_enskog_tgv(case))
-            s.step(steps)
-            s.sync()
-            _, ux, uy = s.moments()
-            res[kappa, N] = _error(case, ux, uy, steps * DT)
-            say(f"kappa {kappa} N {N:3d}: E(u) = {res[kappa, N]:.3e} (paper {paper[N]:.3e})")
     Ns = sorted(paper)
-    for kappa in (1.0, 0.5):
-        orders = [math.log(res[kappa, a] / res[kappa, b]) / math.log(b / a) for a, b in zip(Ns, Ns[1:])]
-        say(f"kappa {kappa}: observed orders " + " ".join(f"{o:.2f}" for o in orders))
-    # the printed form: below the paper's error at the coarse grids and at
-    # least second order; the Taylor form: far above the paper's errors
-    assert res[1.0, 32] < paper[32] and res[1.0, 64] < paper[64]
-    assert math.log2(res[1.0, 32] / res[1.0, 64]) > 2.0
-    assert res[0.5, 32] > 5 * paper[32]
+    res = _table(Ns)
+    for N in Ns:
+        say(f"kappa 1 N {N:3d}: E(u) = {res[N]:.3e} (paper {paper[N]:.3e}, ratio {res[N] / paper[N]:.3f})")
+    orders = _orders(res)
+    say("kappa 1: observed orders " + " ".join(f"{o:.2f}" for o in orders))
+    for N in Ns:
+        assert res[N] < paper[N]
+    for N in (128, 160, 192):
+        assert abs(res[N] / paper[N] - 1.0) < 0.15, N
+    assert abs(orders[-1] - 3.048) < 0.2
+    assert 2.0 < orders[0] < 2.6
+    # the Taylor form of the quadratic term: third order, far above the paper
+    taylor = _table(Ns, taylor_quad=0.5)
+    t_orders = _orders(taylor)
+    say("kappa 1/2: E(u) " + " ".join(f"{taylor[N]:.2e}" for N in Ns) +
+        "; orders " + " ".join(f"{o:.2f}" for o in t_orders))
+    assert all(taylor[N] > 20 * paper[N] for N in Ns)
+    assert all(2.7 < o < 3.2 for o in t_orders)
+
+
+def test_t2s2_rows_of_the_table():
+    # The paper's T2S2 comparison scheme: the Remark-I step with the original
+    # DUGKS reconstruction (S2, variant kernels).  The paper's row is
+    # reproduced within 1% at every N (measured 0.02-0.8%), orders 1.99-2.00.
+    paper = _paper("T2S2")
+    Ns = sorted(paper)
+    res = _table(Ns, scheme=dugks.T2S3, reconstruction=dugks.RECON_S2)
+    for N in Ns:
+        say(f"T2S2 N {N:3d}: E(u) = {res[N]:.4e} (paper {paper[N]:.4e}, ratio {res[N] / paper[N]:.4f})")
+        assert abs(res[N] / paper[N] - 1.0) < 0.01, N
+    assert all(1.95 < o < 2.05 for o in _orders(res))
+
+
+def test_cell_average_reading_on_the_table():
+    # Cell values read as cell averages, two-point Gauss faces (variant
+    # kernels).  With the printed quadratic term the scheme is the printed
+    # point-value scheme seen through the cell-average map: against the cell
+    # averages of the analytic field it gives the same E(u) to 1e-3 relative,
+    # so it does not recover the paper's coarse-grid values either.  With the
+    # Taylor term (exact on quadratics) it is third order but, like the point
+    # form, 50 to 130 times the paper's errors at this Mach number.
+    paper = _paper()
+    Ns = [32, 64, 96]
+    r3 = _table(Ns)
+    avg1 = _table(Ns, avg=True, reconstruction=dugks.RECON_CELL_AVERAGE, taylor_quad=1.0)
+    for N in Ns:
+        say(f"cell average, kappa 1, N {N}: E(u) = {avg1[N]:.4e} (point reading {r3[N]:.4e}, paper {paper[N]:.3e})")
+        assert abs(avg1[N] / r3[N] - 1.0) < 1e-3
+    fine = [128, 160, 192]
+    avgh = _table(fine, avg=True, reconstruction=dugks.RECON_CELL_AVERAGE, taylor_quad=0.5)
+    o = _orders(avgh)
+    say("cell average, kappa 1/2: E(u) " + " ".join(f"{avgh[N]:.3e}" for N in fine) +
+        "; orders " + " ".join(f"{x:.2f}" for x in o))
+    assert all(2.9 < x < 3.15 for x in o)
+    assert all(avgh[N] > 50 * paper[N] for N in fine)
+
+
+def test_family_members_on_the_table():
+    # Other members a of the time-discretization family (printed expansion):
+    # errors within 25% of a = 1/3 at every N (measured: a = 1/2 and 0.42 are
+    # 7-19% lower on coarse grids), the same convergence.
+    Ns = [32, 64, 96, 128]
+    base = _table(Ns)
+    for a in (0.42, 0.5):
+        res = _table(Ns, family_a=a)
+        say(f"a = {a}: E(u) " + " ".join(f"{res[N]:.3e}" for N in Ns) +
+            "; orders " + " ".join(f"{x:.2f}" for x in _orders(res)))
+        for N in Ns:
+            assert abs(res[N] / base[N] - 1.0) < 0.25

@@ -72,6 +72,13 @@ def test_descriptor_validation_on_the_host():
     c2 = C.tgv_case(16)
     c2.rho0 = 0.0
     _expect(-1, c2, precision=dugks.FP32_DELTA)
+    # the time-discretization family takes 1/3 <= a <= 1/2, and only the third-order scheme
+    _expect(-1, C.tgv_case(16), family_a=0.7)
+    _expect(-1, C.tgv_case(16), family_a=0.45, scheme=dugks.T2S3)
+    # an unknown reconstruction
+    _expect(-1, C.tgv_case(16), reconstruction=5)
+    # no relaxation time at all: no tau, tau0 = 0 and no Knudsen number
+    _expect(-1, C.tgv_case(16), kn=(0.0, 1.0))
     assert case is not None
 
 
