@@ -516,6 +516,7 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
     const int nq = Q;
 
     // ---- finish: L = La + equilibrium part (+ deferred wall terms); output --
+    S vrest = 0;   // output of the rest velocity, for the non-finite flag
     [&]<int... qs>(std::integer_sequence<int, qs...>) {
         (([&] {
              constexpr int q = qs;
@@ -532,12 +533,15 @@ sweep_small_body(const SweepParams &p, const double h, const S *__restrict__ X,
                  if (EY < 0 && dsf[3]) L = fmaS((yq * t.cy) * t.an, (S)rw[3] * (S)p.wall_E[3 * nq + q] - r0s, L);
              }
              const S Rq = GENERAL ? out[q * n + ocell] : t.R[q];
-             out[q * n + ocell] = fmaS(aL, L, Rq);
-             // non-finite flag, tested on one velocity (see dugks_sync)
-             if (q == 0 && !__builtin_isfinite(out[q * n + ocell])) *p.bad = 1;
+             const S v = fmaS(aL, L, Rq);
+             out[q * n + ocell] = v;
+             if constexpr (Lat::opp(q) == q) vrest = v;
          }()),
          ...);
     }(Seq{});
+    // non-finite flag: a non-finite value anywhere in the cell's neighbourhood
+    // reaches every velocity through the moments, so the rest velocity is tested
+    if (!__builtin_isfinite(vrest)) *p.bad = 1;
 }
 
 // Single instance: tiles from the block index (XCD-aware order); each kind of

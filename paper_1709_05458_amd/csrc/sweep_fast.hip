@@ -96,6 +96,15 @@ __device__ __forceinline__ void fast_faces(const SweepParams &p, const S *lds, c
     __builtin_amdgcn_sched_barrier(0);
 }
 
+// index of the rest velocity (its own opposite)
+template <class Lat>
+constexpr int rest_velocity()
+{
+    for (int q = 0; q < Lat::Q; q++)
+        if (Lat::opp(q) == q) return q;
+    return 0;
+}
+
 // TF: per-cell relaxation times (a tau field) rather than one tau
 template <class Lat, class S, bool DELTA, bool TF, int STAGE, int TX, int TY>
 __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, const S *__restrict__ X,
@@ -379,11 +388,7 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
     // and odd (linear and cubic) parts
     auto store = [&](int q, S M, S wq) {
         const S r = R0[q];
-        const S v = DELTA ? r + M : fmaS(wq, M, r);
-        *(S *)((char *)(out + (size_t)q * no) + (unsigned)(sizeof(S) * oc)) = v;
-        // a non-finite value anywhere in the cell's neighbourhood reaches
-        // every velocity through the moments, so one velocity is tested
-        if (q == 0 && !__builtin_isfinite(v)) *p.bad = 1;
+        *(S *)((char *)(out + (size_t)q * no) + (unsigned)(sizeof(S) * oc)) = DELTA ? r + M : fmaS(wq, M, r);
     };
     [&]<int... qs>(std::integer_sequence<int, qs...>) {
         (([&] {
@@ -414,6 +419,12 @@ __device__ __forceinline__ void fast_body(const SweepParams &p, const double h, 
          }()),
          ...);
     }(Seq{});
+    // non-finite flag: a non-finite value anywhere in the cell's neighbourhood
+    // reaches every velocity through the moments, so the rest velocity's
+    // output (the value stored above) is tested
+    constexpr int QR = rest_velocity<Lat>();
+    const S vr = DELTA ? R0[QR] + m0 : fmaS((S)p.wtab[Lat::shell(QR)][1], m0, R0[QR]);
+    if (!__builtin_isfinite(vr)) *p.bad = 1;
 }
 
 // Waves per SIMD the register budget is cut for: two where the tile's LDS lets
