@@ -234,8 +234,9 @@ def run_rarefied(args):
     out = {}
     pairs = n * n * vs.nq
     steps = max(3, args.steps // 10)
+    tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
     for prec, name, elem in ((dugks.FP32_DELTA, "fp32", 4), (dugks.FP64, "fp64", 8)):
-        s = dugks.Solver(case, prec, allow_defect=True)
+        s = dugks.Solver(case, prec, allow_defect=True, tile=tile)
         s.init_equilibrium(case.rho, case.ux, case.uy)
         s.step(2)
         s.sync()

@@ -3,6 +3,7 @@
 // and launch sequencing.  Compiled by hipcc as host code.
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -482,6 +483,34 @@ static int check_tau(const double *tau, long long n, double tau0, double dt)
     return DUGKS_OK;
 }
 
+// Ring tiles of the any-size kernels, in order of preference.  A block of
+// tx x ty threads covers (tx - 2) x (ty - 2) cells; every shape here spends
+// about 1.31 threads per cell, so the best shape for a grid is the one that
+// launches the fewest threads (the least padding at the east and north ends).
+static const int kLqTiles[][2] = {{18, 14}, {14, 18}, {16, 16}, {20, 12}, {12, 20}};
+constexpr int LQ_DEFAULT_TILE = 16;
+
+static long long lq_tile_threads(int nx, int ny, int tx, int ty)
+{
+    return (long long)((nx + tx - 3) / (tx - 2)) * ((ny + ty - 3) / (ty - 2)) * tx * ty;
+}
+
+// the shape of kLqTiles with the fewest launched threads over the grids
+// {nx, ny, nq} (weighted by their velocity counts)
+static void lq_pick_tile(const std::vector<std::array<int, 3>> &grids, int &tx, int &ty)
+{
+    long long best = -1;
+    for (const auto &t : kLqTiles) {
+        long long c = 0;
+        for (const auto &g : grids) c += lq_tile_threads(g[0], g[1], t[0], t[1]) * g[2];
+        if (best < 0 || c < best) {
+            best = c;
+            tx = t[0];
+            ty = t[1];
+        }
+    }
+}
+
 int dugks_create(const dugks_desc *din, dugks_t **out)
 {
     if (!out) return fail(DUGKS_EINVAL, "null output handle");
@@ -613,8 +642,9 @@ int dugks_create(const dugks_desc *din, dugks_t **out)
     }
 
     // tile
-    const int dlx = h->lat == 0 ? 16 : (h->lat == 37 && !h->delta ? 16 : 32);
-    const int dly = h->lat == 0 ? 16 : (h->lat == 37 && !h->delta ? 16 : 8);
+    int dlx = h->lat == 37 && !h->delta ? 16 : 32;
+    int dly = h->lat == 37 && !h->delta ? 16 : 8;
+    if (h->lat == 0) lq_pick_tile({{d->nx, d->ny, nq}}, dlx, dly);
     const int lx = d->tile_x > 0 ? d->tile_x : dlx;
     const int ly = d->tile_y > 0 ? d->tile_y : dly;
     const int maxthr = h->lat == 0 ? 256 : 512;
@@ -1323,6 +1353,35 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
             return fail(rc, "instance " + std::to_string(k) + ": " + m);
         }
         b->inst.push_back(c);
+    }
+    {
+        // any-size instances on the library's tile share one shape (the
+        // batched kernels launch blocks of one size): the shape with the
+        // fewest launched threads over all of them
+        std::vector<std::array<int, 3>> grids;
+        auto deflt = [&](int k) {
+            return b->inst[k]->lat == 0 && descs[k].tile_x <= 0 && descs[k].tile_y <= 0;
+        };
+        for (int k = 0; k < n; k++)
+            if (deflt(k)) grids.push_back({descs[k].nx, descs[k].ny, descs[k].nq});
+        int tx = LQ_DEFAULT_TILE, ty = LQ_DEFAULT_TILE;
+        if (!grids.empty()) lq_pick_tile(grids, tx, ty);
+        for (int k = 0; k < n; k++) {
+            if (!deflt(k) || (b->inst[k]->p.tile_x == tx && b->inst[k]->p.tile_y == ty)) continue;
+            dugks_desc dk = descs[k];
+            dk.tile_x = tx;
+            dk.tile_y = ty;
+            dugks_t *c = nullptr;
+            dugks_destroy(b->inst[k]);
+            b->inst[k] = nullptr;
+            if ((rc = dugks_create(&dk, &c))) {
+                const std::string m = g_err;
+                b->inst.erase(b->inst.begin() + k);
+                dugks_destroy(h);
+                return fail(rc, "instance " + std::to_string(k) + ": " + m);
+            }
+            b->inst[k] = c;
+        }
     }
     // parameter table and per-(parity, stage) buffer tables
     std::vector<SweepParams> P;

@@ -79,12 +79,13 @@ def best_tile(case, precision, candidates=CANDIDATES_256, use_cache=True):
 
 
 def tiles_for(cases, precision):
-    """Tuned 256-thread tiles for the lattice instances of a batch (any-size
-    instances keep the library's 16 x 16)."""
+    """Tuned 256-thread tiles for the lattice instances of a batch; None (the
+    library's choice: one ring-tile shape for all of them, the one that
+    launches the fewest threads) for the any-size instances."""
     out = []
     for c in cases:
         if c.vs.name in ("D2Q9", "D2Q37"):
             out.append(best_tile(c, precision))
         else:
-            out.append((16, 16))
+            out.append(None)
     return out

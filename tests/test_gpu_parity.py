@@ -270,6 +270,23 @@ def test_anysize_fp64_one_step_every_element(name, force):
     s.close()
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (18, 14), (14, 18), (20, 12), (12, 20), (8, 8)])
+def test_anysize_ring_tile_shapes(tile):
+    """Every ring-tile shape the library may pick (and a small one) gives the
+    oracle's step on a walled, stretched grid whose sides are not multiples of
+    the tile interior."""
+    case = _mk("nc8_ds_tanh")
+    say(f"[gpu] any-size tile {tile}")
+    o, s = _pair(case, 1.0, tile=tile)
+    assert f"tile {tile[0]}x{tile[1]}" in s.describe()
+    want = o.step(o.init_fhat())
+    s.step(1)
+    s.sync()
+    got = s.get_fhat()
+    assert np.abs(got - want).max() < 1e-13 * np.abs(want).max()
+    s.close()
+
+
 @pytest.mark.parametrize("name,force,steps", [("tgv32_d2q9", True, 100), ("nc8_ds_tanh", False, 40),
                                               ("nc28_cavity_kn1", False, 20)])
 def test_anysize_fp64_many_steps(name, force, steps):
