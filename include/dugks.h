@@ -267,7 +267,12 @@ int dugks_backward_noalloc(dugks_t *h, const double *f0, int nsteps, int ckpt_ev
  * any-size instances, replayed from a HIP graph captured on the first step
  * (a step is one graph launch).  All descriptors share
  * precision and stream; instances of one lattice kind, and all any-size
- * instances, need tiles with the same cell count.  Instance handles from
+ * instances, need tiles with the same cell count (any-size instances left
+ * on the library's tile share one ring-tile shape).  Any-size instances take
+ * velocity chunks of one common length across the batch; an instance whose
+ * chunks then differ from those it takes alone sums its interface moments in
+ * other groups and agrees with its single run to the rounding of those FP64
+ * sums (bit for bit otherwise).  Instance handles from
  * dugks_batch_instance are owned by the batch and serve set_state,
  * init_equilibrium, moments and get_state; stepping one alone makes the
  * next batch step fail with DUGKS_EINVAL.  dugks_sync checks every instance. */

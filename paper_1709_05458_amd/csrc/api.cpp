@@ -1383,6 +1383,41 @@ int dugks_create_batch(int n, const dugks_desc *descs, dugks_t **out)
             b->inst[k] = c;
         }
     }
+    {
+        // Velocity chunks of the any-size instances.  Each instance's own
+        // chunking fills the chip by itself, which gives small instances
+        // chunks of a few velocities; in a batch the instances together fill
+        // the chip, so every instance takes chunks of one common length (about
+        // eight rounds of blocks over the whole batch), never more chunks than
+        // its partial-sum buffers were sized for.
+        long long tile_q = 0, cell_q = 0;   // sums of tiles x velocities and cell blocks x velocities
+        for (dugks *c : b->inst) {
+            if (c->lat != 0) continue;
+            tile_q += (long long)lq_ntile(c->p) * c->p.nq;
+            cell_q += (c->p.ncell + 255) / 256 * c->p.nq;
+        }
+        if (tile_q > 0) {
+            int dev = 0, ncu = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+                ncu = 256;
+            const long long target = 8LL * ncu * 2;   // blocks: eight rounds at two per CU
+            const long long lf = std::max(16LL, tile_q / target), lu = std::max(32LL, cell_q / target);
+            for (dugks *c : b->inst) {
+                if (c->lat != 0) continue;
+                SweepParams &p = c->p;
+                auto rechunk = [&](long long len, int step, int &chunk, int &nchunk) {
+                    const int want = (int)std::max(1LL, std::min<long long>(nchunk, (p.nq + len - 1) / len));
+                    int cl = (p.nq + want - 1) / want;
+                    cl = (cl + step - 1) / step * step;
+                    chunk = cl;
+                    nchunk = (p.nq + cl - 1) / cl;
+                };
+                rechunk(lf, p.lq_qs, p.lq_chunk, p.lq_nchunk);
+                rechunk(lu, 4, p.lq_uchunk, p.lq_nuchunk);
+            }
+        }
+    }
     // parameter table and per-(parity, stage) buffer tables
     std::vector<SweepParams> P;
     std::vector<StageIO> io(4 * (size_t)n);

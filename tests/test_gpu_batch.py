@@ -1,6 +1,7 @@
 """Batched stepping: many uneven instances per launch, replayed from a
 captured graph, must give each instance exactly what it gets alone (same
-kernels, same tiles) and match the oracle."""
+kernels; the small any-size instances here keep their velocity chunks in the
+batch) and match the oracle."""
 import sys
 
 import numpy as np
