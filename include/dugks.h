@@ -240,8 +240,12 @@ int dugks_sync(dugks_t *h);
  * more replaces it.  The adjoint arithmetic is double for both precisions (for
  * DUGKS_FP32_DELTA it linearises around the FP32 trajectory).  No atomics:
  * results are bitwise reproducible.  The handle's state is left unchanged.
- * Periodic uniform grids and the T3S3 scheme only (else DUGKS_ENOTSUP); batch
- * handles: DUGKS_ENOTSUP; nsteps < 0 or ckpt_every < 1: DUGKS_EINVAL. */
+ * Any grid and walls: bounce-back (eq. BB, with the wall cell's density) and
+ * diffuse walls (the diffuse-scattering rule, with its wall density) are
+ * differentiated as the sweep applies them, as are the one-sided stencils
+ * next to walls and the per-cell spacings of stretched grids.  The T3S3
+ * scheme only (else DUGKS_ENOTSUP); batch handles: DUGKS_ENOTSUP; nsteps < 0
+ * or ckpt_every < 1: DUGKS_EINVAL. */
 int dugks_backward(dugks_t *h, const double *f0, int nsteps, int ckpt_every,
                    const double *dL_drho, const double *dL_du,
                    double *dL_df0, double *dL_dtau, int mem);

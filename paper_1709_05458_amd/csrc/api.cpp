@@ -1666,7 +1666,12 @@ struct Arena {
 struct AdjBuffers {
     std::vector<void *> ck, seg;   // checkpoints and the states of one segment
     double *fh_d, *B, *M, *G_d, *B2, *M2, *lam_fbar, *dtf, *lamLs, *lamB, *lamF, *lam[2], *dtau, *tau, *cA, *cC;
+    double *lam_rho = nullptr, *lamBg = nullptr;   // walls and stretched grids
 };
+
+// the adjoint's kernels for walls and stretched grids (the periodic uniform
+// sweep has its own)
+static bool adj_general(const dugks *h) { return !h->p.perx || !h->p.pery || !h->p.uniform; }
 
 static void adj_carve(Arena &ar, const dugks *h, int nseg, int k, AdjBuffers &b)
 {
@@ -1682,8 +1687,16 @@ static void adj_carve(Arena &ar, const dugks *h, int nseg, int k, AdjBuffers &b)
     b.G_d = ar.dbl(nqn);
     b.B2 = ar.dbl(nqn);
     b.M2 = ar.dbl(3 * n);
-    b.lam_fbar = ar.dbl(2 * nqn);
-    b.dtf = ar.dbl(2 * n);
+    // interface adjoints: [axis][q][cell] on periodic uniform grids, [q][face]
+    // over the natural face numbering otherwise
+    const size_t nface = (size_t)(h->p.nx + 1) * h->p.ny + (size_t)h->p.nx * (h->p.ny + 1);
+    const bool gen = adj_general(h);
+    b.lam_fbar = ar.dbl(gen ? (size_t)h->p.nq * nface : 2 * nqn);
+    b.dtf = ar.dbl(gen ? nface : 2 * (size_t)n);
+    if (gen) {
+        b.lam_rho = ar.dbl(nface);
+        b.lamBg = ar.dbl(nqn);
+    }
     b.lamLs = ar.dbl(nqn);
     b.lamB = ar.dbl(nqn);
     b.lamF = ar.dbl(nqn);
@@ -1700,8 +1713,6 @@ static int backward_check(dugks *h, int nsteps, int ckpt_every)
     if (nsteps < 0 || ckpt_every < 1) return fail(DUGKS_EINVAL, "bad arguments");
     if (h->batch) return fail(DUGKS_ENOTSUP, "backward of a batch handle");
     if (h->p.t2 || h->var) return fail(DUGKS_ENOTSUP, "the adjoint is written for the T3S3 scheme");
-    if (!h->p.perx || !h->p.pery || !h->p.uniform)
-        return fail(DUGKS_ENOTSUP, "the adjoint supports periodic uniform grids only");
     return DUGKS_OK;
 }
 
@@ -1739,7 +1750,7 @@ static int backward_core(dugks *h, const double *f0, int nsteps, int ckpt_every,
         t0.assign(n, p.tau0);
         HIPCHECK(hipMemcpyAsync(w.tau, t0.data(), sizeof(double) * n, hipMemcpyHostToDevice, h->stream));
     }
-    {
+    if (!adj_general(h)) {
         // interface window weights in double for both stages (the forward
         // kernels of FP32 storage hold them in float)
         const double dx = 1.0 / p.inv_dx, dy = 1.0 / p.inv_dy;
@@ -1766,6 +1777,28 @@ static int backward_core(dugks *h, const double *f0, int nsteps, int ckpt_every,
     g.cC = w.cC;
     g.h1 = h->h1;
     g.h2 = h->h2;
+    g.general = adj_general(h) ? 1 : 0;
+    g.perx = p.perx;
+    g.pery = p.pery;
+    for (int k = 0; k < 4; k++) {
+        g.bc[k] = p.bc[k];
+        g.uw[k][0] = p.uw[k][0];
+        g.uw[k][1] = p.uw[k][1];
+    }
+    g.opp = p.opp;
+    g.kappa = p.kappa;
+    g.sx_off = p.g.sx_off;
+    g.sy_off = p.g.sy_off;
+    g.sx_d1 = p.g.sx_d1;
+    g.sx_d2 = p.g.sx_d2;
+    g.sy_d1 = p.g.sy_d1;
+    g.sy_d2 = p.g.sy_d2;
+    g.dxl = p.g.dxl;
+    g.dxr = p.g.dxr;
+    g.dyl = p.g.dyl;
+    g.dyr = p.g.dyr;
+    g.inv_dx = p.g.inv_dx;
+    g.inv_dy = p.g.inv_dy;
 
     // forward pass from f0, keeping the state at every k-th step and the last
     HIPCHECK(launch_set_state(p, h->delta, f0, w.ck[0], h->stream));
@@ -1799,7 +1832,8 @@ static int backward_core(dugks *h, const double *f0, int nsteps, int ckpt_every,
             HIPCHECK(adj_launch_prep(g, h->delta, p.rho0, Xt, h->G, w.fh_d, w.B, w.M, w.G_d, w.B2, w.M2,
                                      h->stream));
             HIPCHECK(adj_launch_step(g, w.lam[cur], w.lam[1 - cur], w.fh_d, w.B, w.M, w.G_d, w.B2, w.M2,
-                                     w.lam_fbar, w.dtf, w.lamLs, w.lamB, w.lamF, w.dtau, h->stream));
+                                     w.lam_fbar, w.dtf, w.lamLs, w.lamB, w.lamF, w.dtau, w.lam_rho, w.lamBg,
+                                     h->stream));
             if ((rc = record(h, KC_ADJ_STEP, false))) return rc;
             cur = 1 - cur;
         }

@@ -247,7 +247,8 @@ hipError_t launch_init_eq(const SweepParams &p, bool delta, const double *rho, c
 hipError_t launch_moments(const SweepParams &p, bool delta, const void *state, double *rho,
                           double *ux, double *uy, int *bad, hipStream_t s);
 
-// Discrete adjoint of one step (adjoint.hip): periodic uniform grids, double.
+// Discrete adjoint of one step (adjoint.hip), double: window-weight kernels on
+// periodic uniform grids, general kernels on walls and stretched grids.
 struct AdjArgs {
     int nx, ny, nq;
     long long n;
@@ -256,6 +257,18 @@ struct AdjArgs {
     const double *tau;       // [cell]
     const double *cA, *cC;   // [q][24] interface window weights of stage A / C
     double h1, h2;
+    // walls and stretched grids (the general kernels; the periodic uniform
+    // kernels use the window weights above)
+    int general;
+    int perx, pery;
+    int bc[4];               // DUGKS_BC_* of the W, E, S, N sides
+    double uw[4][2];         // wall velocities
+    const int *opp;          // [q]: index of -xi_q
+    double kappa;            // coefficient of the quadratic term of the expansion
+    const int *sx_off, *sy_off;                    // first stencil offset per column / row
+    const double *sx_d1, *sx_d2, *sy_d1, *sy_d2;   // [3 n]: 3-point derivative weights
+    const double *dxl, *dxr, *dyl, *dyr;           // face offsets from the cell centres
+    const double *inv_dx, *inv_dy;                 // per column / row
 };
 // Primal intermediates of a step from fhat and the stage A output G (storage
 // format): fhat, B and moments at t_n; G, B' and moments at t'.
@@ -263,10 +276,13 @@ hipError_t adj_launch_prep(const AdjArgs &a, bool delta, double rho0, const void
                            double *fh_d, double *B, double *M, double *G_d, double *B2, double *M2,
                            hipStream_t s);
 // lambda_in = (d out / d fhat)^T lambda_out, dtau += (d out / d tau)^T lambda_out.
+// With a.general: lam_fbar [q][face] and dtau_face [face] over the natural
+// face numbering, lam_rho [face] and lamBg [q][cell] as well.
 hipError_t adj_launch_step(const AdjArgs &a, const double *lam_out, double *lam_in, const double *fh_d,
                            const double *B, const double *M, const double *G_d, const double *B2,
                            const double *M2, double *lam_fbar, double *dtau_face, double *lamLs,
-                           double *lamB, double *lamF, double *dtau, hipStream_t s);
+                           double *lamB, double *lamF, double *dtau, double *lam_rho, double *lamBg,
+                           hipStream_t s);
 hipError_t adj_launch_seed(const AdjArgs &a, const double *fh_d, const double *dL_drho, const double *dL_du,
                            double *lam, hipStream_t s);
 hipError_t adj_launch_init(const AdjArgs &a, const double *f0, const double *lam, double *dL_df0,

@@ -125,12 +125,64 @@ def test_adjoint_leaves_state_untouched():
     s.sync()
 
 
-def test_adjoint_rejects_walls():
-    case = C.cavity_case(16, C.d2q9(1.0 / 3.0), re=100.0)
-    s = dugks.Solver(case, dugks.FP64)
-    with pytest.raises(dugks.DugksError) as e:
-        s.backward(_f0(case), 2, 1, None, np.ones((2, 16, 16)))
-    assert e.value.code == -7
+def _walled(kind):
+    """8x8 cases for the adjoint on walls and stretched grids, with a tau
+    field and a perturbed initial flow."""
+    d2q9 = C.d2q9(1.0 / 3.0)
+    if kind == "bounce_back":
+        c = C.cavity_case(8, d2q9, tau=0.05, lid=0.2)
+    elif kind == "diffuse_tanh":
+        c = C.cavity_case(8, d2q9, wall=C.BC_DIFFUSE, grid=C.tanh_grid(8, 8), tau=0.1, lid=0.2)
+    elif kind == "diffuse_nc6_tanh":
+        # tau small enough that dL/dtau stands well above the rounding of the
+        # loss (about 4e-15 absolute here): at tau = 0.2 the flow is nearly
+        # free-molecular, dL/dtau is 2e-4 against 11 for dL/df0, and the
+        # same absolute rounding reads 1.8e-11 relative
+        c = C.cavity_case(8, C.newton_cotes(6, 0.5, renormalize=True), wall=C.BC_DIFFUSE,
+                          grid=C.tanh_grid(8, 8), tau=0.05, lid=0.1, RT=0.5, cfl=0.25)
+    else:   # periodic, stretched along both axes
+        c = C.tgv_case(8, d2q9, nu=0.1)
+        L = 2.0 * math.pi
+        c.grid = C.Grid(L * C.tanh_faces(8, 1.0), L * C.tanh_faces(8, 1.2))
+        c.dt = 0.5 * c.grid.dmin / d2q9.cmax
+    c.tau = C.perturbed_tau(float(c.tau[0, 0]), c.tau.shape, 0.1, 31)
+    z = C.normal(32, 3 * c.ncell).reshape(3, c.grid.ny, c.grid.nx)
+    c.rho = c.rho + 0.01 * z[0]
+    c.ux = c.ux + 0.02 * z[1]
+    c.uy = c.uy + 0.02 * z[2]
+    return c
+
+
+@pytest.mark.parametrize("kind", ["bounce_back", "diffuse_tanh", "diffuse_nc6_tanh", "periodic_stretched"])
+def test_adjoint_walls_and_stretched_grids_vs_oracle_complex_step(kind):
+    """Every component of dL/df0 and dL/dtau, 3 steps, on walled cavities
+    (bounce-back with a moving lid, diffuse walls on a tanh grid with D2Q9
+    and with a Newton-Cotes set) and on a periodic stretched grid: the
+    one-sided stencils, the wall rules and their densities, per-cell spacings."""
+    case = _walled(kind)
+    f0 = _f0(case)
+    ny, nx = case.tau.shape
+    nsteps, hcs = 3, 1e-30
+    a = C.normal(41, nx * ny).reshape(ny, nx)
+    b = C.normal(42, 2 * nx * ny).reshape(2, ny, nx)
+    s = dugks.Solver(case, dugks.FP64, allow_defect=abs(case.vs.moment_defect()["sum_w_minus_1"]) > 1e-10)
+    say(f"[gpu] adjoint {kind}: {s.describe()}")
+    gf, gt = s.backward(f0, nsteps, 2, a, b)
+    ref_f = np.empty_like(f0)
+    for k in range(f0.size):
+        df = np.zeros(f0.size, dtype=complex)
+        df[k] = 1j * hcs
+        ref_f.flat[k] = _oracle_loss_cs(case, f0 + df.reshape(f0.shape), case.tau, nsteps, a, b).imag / hcs
+    ref_t = np.empty_like(case.tau)
+    for k in range(case.tau.size):
+        dt = np.zeros(case.tau.size, dtype=complex)
+        dt[k] = 1j * hcs
+        ref_t.flat[k] = _oracle_loss_cs(case, f0.astype(complex), case.tau + dt.reshape(case.tau.shape),
+                                        nsteps, a, b).imag / hcs
+    ef = np.abs(gf - ref_f).max() / np.abs(ref_f).max()
+    et = np.abs(gt - ref_t).max() / np.abs(ref_t).max()
+    say(f"    rel err f0 {ef:.2e}, tau {et:.2e}")
+    assert ef < 1e-11 and et < 1e-11
 
 
 # ---------------------------------------------------------------------------
