@@ -90,29 +90,92 @@ __device__ __forceinline__ double eq_val(const AdjArgs &a, int q, double rho, do
                            0.5 * (ux * ux + uy * uy) * a.iRT);
 }
 
+// The lane's k-th velocity q = s + AL k.  Past the last velocity it is
+// clamped to the last one and marked off: its loads stay in bounds and its
+// terms are dropped, so that with the velocity count fixed at compile time the
+// loop has a fixed trip count (used where a lane loads one value per
+// velocity; the face and cell kernels, whose loads per velocity are windows
+// of 12 or 24 values, keep a loop that stops at the last velocity, since
+// issuing every window at once took more registers than it saved).
+struct Vel {
+    int q;
+    bool on;
+};
+__device__ __forceinline__ Vel vel_of(const Lane &L, int k, int nq)
+{
+    const int q = L.s + AL * k;
+    return q < nq ? Vel{q, true} : Vel{nq - 1, false};
+}
+
 // ---------------------------------------------------------------------------
 // Primal intermediates of one step from fhat (storage units) and G (stage A
 // output): B, moments of fhat, B' and moments of G, all in double.
 // ---------------------------------------------------------------------------
-template <class S, bool DELTA>
-__global__ void adj_prep(const AdjArgs a, double rho0, const S *__restrict__ fhat, const S *__restrict__ G,
-                         double *__restrict__ fh_d, double *__restrict__ B, double *__restrict__ M,
-                         double *__restrict__ G_d, double *__restrict__ B2, double *__restrict__ M2)
+template <class S, bool DELTA, int QC>
+__global__ void __launch_bounds__(AL * AC) adj_prep(const AdjArgs a, double rho0, const S *__restrict__ fhat,
+                                                    const S *__restrict__ G, double *__restrict__ fh_d,
+                                                    double *__restrict__ B, double *__restrict__ M,
+                                                    double *__restrict__ G_d, double *__restrict__ B2,
+                                                    double *__restrict__ M2)
 {
     const Lane L = lane_of(a.n);
     const long long c = L.c;
     const double tau = a.tau[c], dt = a.dt;
     const double c1 = (12.0 * tau - dt) / (12.0 * tau + 3.0 * dt);
     const double c3 = (24.0 * tau - 5.0 * dt) / (24.0 * tau + 4.0 * dt);
+    auto val = [&](const S *src, int q) {
+        return DELTA ? a.w[q] * ((double)src[q * a.n + c] + rho0) : (double)src[q * a.n + c];
+    };
+    if constexpr (QC > 0) {
+        // both states' values of the lane's velocities, loaded together; one
+        // sum over the waves for both sets of moments
+        constexpr int NR = (QC + AL - 1) / AL;
+        double vf[NR], vg[NR];
+#pragma unroll
+        for (int k = 0; k < NR; k++) {
+            const Vel V = vel_of(L, k, QC);
+            vf[k] = val(fhat, V.q);
+            vg[k] = val(G, V.q);
+        }
+        double m6[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < NR; k++) {
+            const Vel V = vel_of(L, k, QC);
+            const double f = V.on ? vf[k] : 0.0, g = V.on ? vg[k] : 0.0;
+            m6[0] += f;
+            m6[1] += a.xi[V.q] * f;
+            m6[2] += a.eta[V.q] * f;
+            m6[3] += g;
+            m6[4] += a.xi[V.q] * g;
+            m6[5] += a.eta[V.q] * g;
+        }
+        wave_sum(m6);
+        if (!L.ok) return;
+        if (L.s == 0) {
+            for (int k = 0; k < 3; k++) {
+                M[3 * c + k] = m6[k];
+                M2[3 * c + k] = m6[3 + k];
+            }
+        }
+        const double ux = m6[1] / m6[0], uy = m6[2] / m6[0], gx = m6[4] / m6[3], gy = m6[5] / m6[3];
+#pragma unroll
+        for (int k = 0; k < NR; k++) {
+            const Vel V = vel_of(L, k, QC);
+            if (!V.on) break;
+            const long long o = (long long)V.q * a.n + c;
+            fh_d[o] = vf[k];
+            G_d[o] = vg[k];
+            B[o] = c1 * vf[k] + (1.0 - c1) * eq_val(a, V.q, m6[0], ux, uy);
+            B2[o] = c3 * vg[k] + (1.0 - c3) * eq_val(a, V.q, m6[3], gx, gy);
+        }
+        return;
+    }
     for (int pass = 0; pass < 2; pass++) {
         const S *src = pass ? G : fhat;
         double *dst = pass ? G_d : fh_d;
-        auto val = [&](int q) {
-            return DELTA ? a.w[q] * ((double)src[q * a.n + c] + rho0) : (double)src[q * a.n + c];
-        };
         double r = 0, mx = 0, my = 0;
         for (int q = L.s; q < a.nq; q += AL) {
-            const double v = val(q);
+            const double v = val(src, q);
             if (L.ok) dst[q * a.n + c] = v;
             r += v;
             mx += a.xi[q] * v;
@@ -132,7 +195,7 @@ __global__ void adj_prep(const AdjArgs a, double rho0, const S *__restrict__ fha
         const double ux = mx / r, uy = my / r, cc = pass ? c3 : c1;
         double *Bo = pass ? B2 : B;
         for (int q = L.s; q < a.nq; q += AL)
-            if (L.ok) Bo[q * a.n + c] = cc * val(q) + (1.0 - cc) * eq_val(a, q, r, ux, uy);
+            if (L.ok) Bo[q * a.n + c] = cc * val(src, q) + (1.0 - cc) * eq_val(a, q, r, ux, uy);
     }
 }
 
@@ -741,11 +804,18 @@ static inline dim3 gc(long long n, int rows = 1) { return dim3((unsigned)((n + A
 hipError_t adj_launch_prep(const AdjArgs &a, bool delta, double rho0, const void *fhat, const void *G,
                            double *fh_d, double *B, double *M, double *G_d, double *B2, double *M2, hipStream_t s)
 {
-    if (delta)
-        hipLaunchKernelGGL((adj_prep<float, true>), gc(a.n), dim3(AL * AC), 0, s, a, rho0, (const float *)fhat,
+    // the velocity count fixed at compile time for D2Q9
+    if (delta && a.nq == 9)
+        hipLaunchKernelGGL((adj_prep<float, true, 9>), gc(a.n), dim3(AL * AC), 0, s, a, rho0, (const float *)fhat,
                            (const float *)G, fh_d, B, M, G_d, B2, M2);
+    else if (delta)
+        hipLaunchKernelGGL((adj_prep<float, true, 0>), gc(a.n), dim3(AL * AC), 0, s, a, rho0, (const float *)fhat,
+                           (const float *)G, fh_d, B, M, G_d, B2, M2);
+    else if (a.nq == 9)
+        hipLaunchKernelGGL((adj_prep<double, false, 9>), gc(a.n), dim3(AL * AC), 0, s, a, rho0, (const double *)fhat,
+                           (const double *)G, fh_d, B, M, G_d, B2, M2);
     else
-        hipLaunchKernelGGL((adj_prep<double, false>), gc(a.n), dim3(AL * AC), 0, s, a, rho0, (const double *)fhat,
+        hipLaunchKernelGGL((adj_prep<double, false, 0>), gc(a.n), dim3(AL * AC), 0, s, a, rho0, (const double *)fhat,
                            (const double *)G, fh_d, B, M, G_d, B2, M2);
     return hipGetLastError();
 }
