@@ -22,13 +22,16 @@ LIB_CS = os.path.join(HERE, "liboracle_cs.so")
 
 
 def build(force: bool = False) -> None:
-    """Compile the oracle twice: real (double) and complex-step (double complex)."""
+    """Compile the oracle twice: real (double) and complex-step (double
+    complex); and the three-dimensional oracle (oracle3d.py)."""
     base = ["gcc", "-std=gnu11", "-O2", "-fPIC", "-shared", "-fopenmp", SRC, "-lm"]
     for out, extra in ((LIB, []), (LIB_CS, ["-DORACLE_COMPLEX"])):
         if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(SRC):
             tmp = out + ".tmp"
             subprocess.check_call(base[:1] + extra + base[1:] + ["-o", tmp])
             os.replace(tmp, out)
+    from . import oracle3d
+    oracle3d.build(force)
 
 
 class _OcCase(ctypes.Structure):

@@ -502,3 +502,103 @@ def batch_cases(n: int = 64, seed: int = 4, nmin: int = 32, nmax: int = 256,
         c.meta.update({"Kn": kn, "cfl": cfl})
         out.append(c)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Three space dimensions: velocity sets, the periodic box and its flows.
+# A VelocitySet here holds xi with shape (3, Q).
+# ---------------------------------------------------------------------------
+def d3q27(RT: float) -> VelocitySet:
+    """Tensor product of the 3-point Gauss-Hermite rule in three dimensions
+    (weights (1/6, 2/3, 1/6) per axis, c = sqrt(3 RT)); q = 9 ix + 3 iy + iz
+    over the components (-c, 0, c)."""
+    c = math.sqrt(3.0 * RT)
+    e1 = np.array([-1.0, 0.0, 1.0])
+    w1 = np.array([1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0])
+    ix, iy, iz = np.meshgrid(np.arange(3), np.arange(3), np.arange(3), indexing="ij")
+    ix, iy, iz = ix.reshape(-1), iy.reshape(-1), iz.reshape(-1)
+    xi = np.stack([e1[ix], e1[iy], e1[iz]]) * c
+    w = w1[ix] * w1[iy] * w1[iz]
+    return VelocitySet("D3Q27", xi, w, RT)
+
+
+def d3q19(RT: float) -> VelocitySet:
+    """The 19 velocities of D3Q27 with at most two nonzero components, weights
+    1/3 (rest), 1/18 (one component) and 1/36 (two), c = sqrt(3 RT): they
+    reproduce the isothermal Gaussian moments up to fourth order that the
+    second-order equilibrium needs.  Order: that of D3Q27 with the eight
+    corner velocities left out."""
+    full = d3q27(RT)
+    nz = np.count_nonzero(np.abs(full.xi) > 0, axis=0)
+    keep = nz <= 2
+    wt = np.array([1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0])
+    return VelocitySet("D3Q19", full.xi[:, keep], wt[nz[keep]], RT)
+
+
+@dataclass
+class Case3:
+    """A triply periodic box of uniform cells, velocity set, tau field and
+    initial macroscopic state, arrays [z][y][x]."""
+
+    name: str
+    n: tuple                 # (nx, ny, nz)
+    L: tuple                 # (Lx, Ly, Lz)
+    vs: VelocitySet
+    dt: float
+    tau: np.ndarray          # (nz, ny, nx)
+    rho: np.ndarray          # (nz, ny, nx)
+    u: np.ndarray            # (3, nz, ny, nx)
+    rho0: float = 1.0
+    steps: int = 1
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ncell(self) -> int:
+        return self.n[0] * self.n[1] * self.n[2]
+
+    @property
+    def h(self) -> tuple:
+        return tuple(self.L[a] / self.n[a] for a in range(3))
+
+    def centres(self):
+        """Cell-centre coordinates X, Y, Z, each (nz, ny, nx)."""
+        ax = [(np.arange(self.n[a]) + 0.5) * self.h[a] for a in range(3)]
+        Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+        return X, Y, Z
+
+
+def abc_fields(X, Y, Z, u0: float, RT: float, rho0: float = 1.0):
+    """Arnold-Beltrami-Childress flow with A = B = C = 1 on [0, 2 pi]^3,
+    scaled to peak speed component u0: u = (u0/2)(sin z + cos y,
+    sin x + cos z, sin y + cos x).  It is a Beltrami field (curl u = u), so
+    u.grad u = grad |u|^2/2 and the incompressible flow decays as
+    exp(-nu t) with p = -rho0 |u|^2 / 2; the density follows the
+    isothermal law rho = rho0 + p / RT."""
+    a = 0.5 * u0
+    u = np.stack([a * (np.sin(Z) + np.cos(Y)), a * (np.sin(X) + np.cos(Z)), a * (np.sin(Y) + np.cos(X))])
+    rho = rho0 - rho0 * (u * u).sum(axis=0) / (2.0 * RT)
+    return rho, u
+
+
+def abc_case(n: int, vs: VelocitySet | None = None, nu: float = 0.01, ma: float = 0.05,
+             cfl: float = 0.5, noise: float = 0.0, seed: int = 1709054583, steps: int = 100,
+             RT: float = 1.0 / 3.0, shape: tuple | None = None) -> Case3:
+    """ABC flow on [0, 2 pi]^3 (n cells per side, or `shape` = (nx, ny, nz)
+    cells over the same box), u0 = Ma sqrt(3 RT), tau = nu / RT,
+    dt = cfl dx / C; optional additive noise noise*u0*N(0,1) per cell and
+    component (seeded)."""
+    vs = vs if vs is not None else d3q19(RT)
+    shape = tuple(shape) if shape is not None else (n, n, n)
+    L = (2.0 * math.pi,) * 3
+    c = Case3("", shape, L, vs, 0.0, np.zeros(0), np.zeros(0), np.zeros(0))
+    X, Y, Z = c.centres()
+    u0 = ma * math.sqrt(3.0 * RT)
+    rho, u = abc_fields(X, Y, Z, u0, RT)
+    if noise:
+        u = u + noise * u0 * normal(seed, u.size).reshape(u.shape)
+    c.name = f"abc{shape[0]}x{shape[1]}x{shape[2]}_{vs.name}"
+    c.dt = cfl * min(c.h) / vs.cmax
+    c.tau = np.full(rho.shape, nu / RT)
+    c.rho, c.u, c.steps = rho, u, steps
+    c.meta = {"u0": u0, "nu": nu, "noise": noise, "seed": seed}
+    return c
