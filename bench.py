@@ -88,12 +88,15 @@ def parse():
     ap.add_argument("--scheme", default="t3s3", choices=["t3s3", "t2s3"],
                     help="time integrator of the Taylor-Green workload (t2s3: the paper's second-order "
                          "comparison scheme, one sweep per step)")
-    ap.add_argument("--workload", default="tgv", choices=["tgv", "batched", "rarefied", "adjoint", "cavity"],
+    ap.add_argument("--workload", default="tgv", choices=["tgv", "batched", "rarefied", "adjoint", "cavity", "abc3d"],
                     help="tgv: Taylor-Green (headline); batched: 64 uneven cavities in one graph "
                          "launch per step; rarefied: Newton-Cotes cavity on stretched cells; adjoint: "
                          "gradient of 500 Taylor-Green 256^2 D2Q9 steps (dugks_backward); cavity: "
                          "lid-driven cavity at Re 1000 with bounce-back walls (--n, --lattice, --tile; 16x16 "
-                         "by default)")
+                         "by default); abc3d: the three-dimensional sweep on the ABC flow, 128^3 cells, D3Q19 "
+                         "(--n3, --lattice3)")
+    ap.add_argument("--n3", type=int, default=128, help="cells per side (abc3d)")
+    ap.add_argument("--lattice3", default="d3q19", choices=["d3q19", "d3q27"])
     ap.add_argument("--nc", type=int, default=101, help="Newton-Cotes points per axis (rarefied)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates HBM byte counters)")
@@ -406,6 +409,67 @@ def run_cavity(args):
             "roofline": roofline, "cpu_baseline": None}
 
 
+def run_abc3d(args):
+    """Three-dimensional sweep on the Arnold-Beltrami-Childress flow: a
+    triply periodic box of n^3 uniform cells on [0, 2 pi]^3, D3Q19 or D3Q27,
+    nu = 0.01, Ma 0.05, CFL 0.5; FP32-delta with FP64 beside it, the same
+    steps from the same equilibrium start."""
+    import torch
+    from paper_1709_05458_amd import cases as C, dugks
+    vs = getattr(C, args.lattice3)(1.0 / 3.0)
+    case = C.abc_case(args.n3, vs, nu=0.01, ma=0.05, cfl=0.5)
+    pairs = case.ncell * vs.nq
+    out = {}
+    for prec, name in ((dugks.FP32_DELTA, "fp32"), (dugks.FP64, "fp64")):
+        s = dugks.Solver3D(case, prec)
+        s.init_equilibrium(case.rho, case.u)
+        r0, u0 = s.moments()
+        s.step(args.warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.step(args.steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        a_ms, c_ms = s.step_timed(10)   # kernel time per stage, HIP events on the library's stream
+        r, u = s.moments()
+        if not np.isfinite(r).all():
+            raise RuntimeError("non-finite state")
+        out[name] = {"value": round(pairs / (ms * 1e-3) / 1e9, 3), "ms_per_step": round(ms, 5),
+                     "stage_a_ms": round(a_ms, 5), "stage_c_ms": round(c_ms, 5),
+                     "mass_rel_drift": abs(float(r.sum()) - float(r0.sum())) / float(r0.sum()),
+                     "_u": tuple(u)}
+        s.close()
+    gap = precision_gap(out["fp32"].pop("_u"), out["fp64"].pop("_u"))
+    r32 = out["fp32"]
+    # dominant stage; algorithmic bytes as for the two-dimensional sweep: stage
+    # C reads fhat and tilde f and writes fhat (3 stored elements per pair),
+    # stage A reads fhat and writes tilde f (2).  The kernels also move the
+    # transformed states B of both stages (design traffic, not counted).
+    dom = "C" if r32["stage_c_ms"] >= r32["stage_a_ms"] else "A"
+    dom_ms = r32["stage_c_ms"] if dom == "C" else r32["stage_a_ms"]
+    bytes_dom = (3 if dom == "C" else 2) * 4 * pairs
+    achieved = bytes_dom / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": f"stage {dom} (k3_stage, STAGE={1 if dom == 'C' else 0})",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": bytes_dom, "launch_ms": round(dom_ms, 5),
+                "stage_a_ms": r32["stage_a_ms"], "stage_c_ms": r32["stage_c_ms"]}
+    n = args.n3
+    return {"metric": METRIC, "value": r32["value"], "unit": UNIT, "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": r32["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"ABC flow {n}x{n}x{n} periodic, {vs.name}, nu 0.01, Ma 0.05, FP32-delta "
+                                   "storage, T3S3 (three-dimensional sweep)", "pairs": pairs},
+            "fp64": out["fp64"],
+            "checks": {"fp32_mass_rel_drift": r32["mass_rel_drift"],
+                       "fp64_mass_rel_drift": out["fp64"]["mass_rel_drift"],
+                       "fp32_vs_fp64": dict(gap, steps_total=args.warmup + args.steps + 10)},
+            "roofline": roofline, "cpu_baseline": None}
+
+
 def cpu_baseline(lattice):
     """The oracle as it stands on the host cores, on a bounded sample of the
     same workload (Taylor-Green, same velocity set, 256 x 256, a few steps)."""
@@ -449,6 +513,9 @@ def main():
         return
     if args.workload == "cavity":
         print(json.dumps(run_cavity(args)))
+        return
+    if args.workload == "abc3d":
+        print(json.dumps(run_abc3d(args)))
         return
     tile = tuple(int(v) for v in args.tile.split("x")) if args.tile else None
     case = make_case(args.n, args.lattice)

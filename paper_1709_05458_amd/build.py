@@ -20,6 +20,7 @@ LATTICE_VARIANTS = [(9, 1), (9, 0), (37, 1), (37, 0)]
 UNITS = ([("sweep.hip", lat, d) for lat, d in LATTICE_VARIANTS] +
          [("sweep_fast.hip", lat, d) for lat, d in LATTICE_VARIANTS] +
          [("sweep_large.hip", None, None), ("aux.hip", None, None), ("adjoint.hip", None, None),
+          ("sweep3d.hip", None, None),
           ("variant.hip", None, None), ("dispatch.hip", None, None), ("api.cpp", None, None)])
 # -packed-fp32-ops: no packed FP32 instructions are generated.
 FLAGS = ["-O3", "-std=c++20", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-function",

@@ -101,6 +101,9 @@ static int fail(int code, const std::string &msg)
     return code;
 }
 
+// the same record for the other C-ABI sources of the library
+int dk::set_error(int code, const char *msg) { return fail(code, msg); }
+
 #define HIPCHECK(expr)                                                                     \
     do {                                                                                   \
         hipError_t e_ = (expr);                                                            \

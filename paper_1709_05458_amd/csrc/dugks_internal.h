@@ -5,6 +5,10 @@
 
 namespace dk {
 
+// Records msg as the calling thread's last error (dugks_last_error_message)
+// and returns code.
+int set_error(int code, const char *msg);
+
 // Geometry tables for the general (walls / non-uniform) reconstruction path.
 // All device pointers.  Periodic neighbours are expressed through the face
 // offsets dxl/dxr, which already include the periodic image shift.

@@ -53,6 +53,17 @@ class DugksDesc(ctypes.Structure):
                 ("dev_alloc", c_void_p), ("dev_free", c_void_p), ("alloc_ctx", c_void_p)]
 
 
+class Dugks3dDesc(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int), ("nz", c_int),
+                ("lx", c_double), ("ly", c_double), ("lz", c_double),
+                ("nq", c_int),
+                ("xi", POINTER(c_double)), ("w", POINTER(c_double)),
+                ("RT", c_double), ("dt", c_double),
+                ("tau", POINTER(c_double)), ("tau0", c_double),
+                ("precision", c_int), ("rho0", c_double), ("taylor_quad", c_double),
+                ("stream", c_void_p)]
+
+
 _lib = None
 
 
@@ -84,6 +95,15 @@ def lib():
             "dugks_create_batch": ([ip, POINTER(DugksDesc), POINTER(c_void_p)], ip),
             "dugks_batch_size": ([vp, POINTER(c_int)], ip),
             "dugks_batch_instance": ([vp, ip, POINTER(c_void_p)], ip),
+            "dugks3d_create": ([POINTER(Dugks3dDesc), POINTER(c_void_p)], ip),
+            "dugks3d_destroy": ([vp], ip),
+            "dugks3d_set_state": ([vp, vp, ip], ip),
+            "dugks3d_init_equilibrium": ([vp, vp, vp, ip], ip),
+            "dugks3d_step": ([vp, ip], ip),
+            "dugks3d_step_timed": ([vp, ip, dp, dp], ip),
+            "dugks3d_moments": ([vp, vp, vp, ip], ip),
+            "dugks3d_get_fhat": ([vp, vp, ip], ip),
+            "dugks3d_get_state": ([vp, vp, ip], ip),
             "dugks_strerror": ([ip], c_char_p),
             "dugks_last_error_message": ([], c_char_p),
         }
@@ -459,3 +479,91 @@ class BatchSolver:
             self.close()
         except Exception:
             pass
+
+
+class Solver3D:
+    """One three-dimensional solver (a dugks3d_t handle) on a triply periodic
+    box of uniform cells, from a cases.Case3; arrays [q][z][y][x]."""
+
+    def __init__(self, case, precision: int = FP64, taylor_quad: float = 1.0, stream=None):
+        vs = case.vs
+        self.case = case
+        self.nx, self.ny, self.nz = case.n
+        self.nq = vs.nq
+        self.ncell = case.ncell
+        self.shape = (self.nz, self.ny, self.nx)
+        tau = np.asarray(case.tau, dtype=np.float64)
+        self._keep = [np.ascontiguousarray(vs.xi.reshape(-1), dtype=np.float64),
+                      np.ascontiguousarray(vs.w, dtype=np.float64),
+                      np.ascontiguousarray(np.broadcast_to(tau, self.shape).reshape(-1))]
+        d = Dugks3dDesc()
+        d.nx, d.ny, d.nz = case.n
+        d.lx, d.ly, d.lz = case.L
+        d.nq = vs.nq
+        d.xi, d.w = _dptr(self._keep[0]), _dptr(self._keep[1])
+        d.RT, d.dt = vs.RT, case.dt
+        d.tau, d.tau0 = _dptr(self._keep[2]), float(self._keep[2].mean())
+        d.precision = precision
+        d.rho0 = float(case.rho0)
+        d.taylor_quad = taylor_quad
+        stream = _default_stream() if stream is None else stream
+        d.stream = c_void_p(stream) if stream else None
+        self.desc = d
+        h = c_void_p()
+        check(lib().dugks3d_create(byref(d), byref(h)), "dugks3d_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().dugks3d_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, f):
+        p, mem, keep = _ptr_mem(f)
+        check(lib().dugks3d_set_state(self.h, p, mem), "dugks3d_set_state")
+
+    def init_equilibrium(self, rho, u):
+        pr, mr, kr = _ptr_mem(rho)
+        pu, mu, ku = _ptr_mem(u)
+        if mr != mu:
+            raise ValueError("rho and u must live in the same memory")
+        check(lib().dugks3d_init_equilibrium(self.h, pr, pu, mr), "dugks3d_init_equilibrium")
+
+    def step(self, n: int = 1):
+        check(lib().dugks3d_step(self.h, int(n)), "dugks3d_step")
+
+    def step_timed(self, n: int):
+        """Advance n steps with HIP events around each launch; returns the mean
+        (stage A ms, stage C ms)."""
+        a, c = c_double(), c_double()
+        check(lib().dugks3d_step_timed(self.h, int(n), byref(a), byref(c)), "dugks3d_step_timed")
+        return a.value, c.value
+
+    def moments(self):
+        """(rho (nz, ny, nx), u (3, nz, ny, nx)) as numpy arrays."""
+        r = np.empty(self.ncell)
+        u = np.empty(3 * self.ncell)
+        check(lib().dugks3d_moments(self.h, c_void_p(r.ctypes.data), c_void_p(u.ctypes.data), MEM_HOST),
+              "dugks3d_moments")
+        return r.reshape(self.shape), u.reshape((3,) + self.shape)
+
+    def _dist(self, fn, out):
+        if out is not None:
+            p, mem, keep = _ptr_mem(out)
+            check(fn(self.h, p, mem), fn.__name__)
+            return out
+        f = np.empty(self.nq * self.ncell)
+        check(fn(self.h, c_void_p(f.ctypes.data), MEM_HOST), fn.__name__)
+        return f.reshape((self.nq,) + self.shape)
+
+    def get_state(self, out=None):
+        return self._dist(lib().dugks3d_get_state, out)
+
+    def get_fhat(self, out=None):
+        return self._dist(lib().dugks3d_get_fhat, out)

@@ -1,6 +1,6 @@
 """Host-side checks of the C-ABI library: it loads without a GPU, exports
-every symbol include/dugks.h declares, and rejects invalid descriptors before
-touching the device."""
+every symbol include/dugks.h and include/dugks3d.h declare, and rejects invalid
+descriptors before touching the device."""
 import os
 import re
 
@@ -10,21 +10,53 @@ import pytest
 from paper_1709_05458_amd import cases as C
 from paper_1709_05458_amd import dugks
 
-HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "dugks.h")
+INC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+HDR = os.path.join(INC, "dugks.h")
 
 
-def declared_functions():
-    src = open(HDR).read()
+def declared_functions(path=HDR):
+    src = open(path).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(dugks_[a-z_0-9]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(dugks3?d?_[a-z_0-9]+)\s*\(", src)))
 
 
 def test_every_declared_symbol_is_exported():
     names = declared_functions()
     assert len(names) >= 15
+    names3 = declared_functions(os.path.join(INC, "dugks3d.h"))
+    assert len(names3) >= 9 and all(n.startswith("dugks3d_") for n in names3)
     L = dugks.lib()
-    for n in names:
+    for n in names + names3:
         assert hasattr(L, n), n
+
+
+def test_3d_descriptor_validation_on_the_host():
+    def expect(code, case, **kw):
+        with pytest.raises(dugks.DugksError) as e:
+            dugks.Solver3D(case, **kw)
+        assert e.value.code == code, str(e.value)
+
+    RT = 1.0 / 3.0
+    bad = C.abc_case(8, C.d3q19(RT))
+    bad.tau = np.full(bad.tau.shape, bad.dt / 12.5)     # beyond dt/tau <= 12
+    expect(-2, bad)
+    bad = C.abc_case(8, C.d3q19(RT), cfl=1.5)           # CFL above 1
+    expect(-1, bad)
+    bad = C.abc_case(8, C.d3q27(RT), shape=(8, 2, 8))   # too few cells
+    expect(-1, bad)
+    c2 = C.abc_case(8, C.d3q19(RT))
+    c2.rho0 = 0.0
+    expect(-1, c2, precision=dugks.FP32_DELTA)
+    vs = C.d3q19(RT)
+    vs.w = vs.w * 1.01                                  # weights not moment-exact
+    expect(-3, C.abc_case(8, vs))
+    vs15 = C.d3q27(RT)                                  # a set of neither 19 nor 27 velocities
+    keep = np.count_nonzero(vs15.xi, axis=0) != 2
+    vs15 = C.VelocitySet("D3Q15", vs15.xi[:, keep], np.where(np.count_nonzero(vs15.xi[:, keep], axis=0) == 0,
+                                                             2.0 / 9.0, np.where(np.count_nonzero(
+                                                                 vs15.xi[:, keep], axis=0) == 1, 1.0 / 9.0,
+                                                                 1.0 / 72.0)), RT)
+    expect(-7, C.abc_case(8, vs15))
 
 
 def test_strerror_covers_codes():
