@@ -451,7 +451,7 @@ def run_abc3d(args):
     dom_ms = r32["stage_c_ms"] if dom == "C" else r32["stage_a_ms"]
     bytes_dom = (3 if dom == "C" else 2) * 4 * pairs
     achieved = bytes_dom / (dom_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": f"stage {dom} (k3_stage, STAGE={1 if dom == 'C' else 0})",
+    roofline = {"bound": "hbm", "kernel": f"stage {dom} (k3_stage_lat, STAGE={1 if dom == 'C' else 0})",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "bytes_per_launch": bytes_dom, "launch_ms": round(dom_ms, 5),

@@ -60,7 +60,7 @@ typedef struct {
  * dt/tau <= 12 (DUGKS_EUNSTABLE; the paper's stability bound at a = 1/3,
  * section "Time discretization"), sum w = 1, sum w xi = 0 and
  * sum w xi xi = RT I within 1e-10 (DUGKS_EMOMENT), nq in {19, 27}
- * (DUGKS_ENOTSUP).  On success *out owns four device arrays of nq cells
+ * (DUGKS_ENOTSUP).  On success *out owns four device arrays of nq x cells
  * values in the storage precision (the state, the transformed state of each
  * stage, the stage output) plus 9 doubles per cell (two sets of moments and
  * tau); the state is undefined until set_state or init_equilibrium. */
@@ -77,7 +77,13 @@ int dugks3d_set_state(dugks3d_t *h, const double *f, int mem);
 int dugks3d_init_equilibrium(dugks3d_t *h, const double *rho, const double *u, int mem);
 
 /* Advance nsteps T3S3 steps (asynchronous on the stream): two kernels per
- * step, one per stage, each over tiles of 8 x 8 x 4 cells. */
+ * step, one per stage, each over tiles of 8 x 8 x 4 cells.  Velocity sets
+ * equal to the library's D3Q19 or D3Q27 (xi = c e_q with e_q in the order of
+ * cases.d3q27: q = 9 (ex+1) + 3 (ey+1) + (ez+1), D3Q19 the same order without
+ * the eight corners; the standard weights) run kernels specialised at
+ * compile time; any other set of 19 or 27 velocities runs kernels that read
+ * the interface-expansion windows from tables.  Both give the oracle's
+ * results to rounding. */
 int dugks3d_step(dugks3d_t *h, int nsteps);
 
 /* As dugks3d_step, with HIP events around every launch; synchronises and

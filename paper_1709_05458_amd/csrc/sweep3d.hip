@@ -32,6 +32,7 @@
 #include <cmath>
 #include <map>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/dugks3d.h"
@@ -60,6 +61,7 @@ struct Args {
     const int *woff;    // [2][3][Q][MAXW] LDS offset of each entry from the cell's own slot
     const double *wd;   // [2][3][Q][MAXW] weights
     const float *wf;
+    double cs;          // lattice kernels: xi = cs e_q
 };
 
 __device__ __forceinline__ int wrapn(int v, int n) { return ((v % n) + n) % n; }
@@ -325,6 +327,359 @@ __global__ void __launch_bounds__(NT) k3_stage(const Args a, const S *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// The same stage for the library's lattices (D3Q27: xi = c e with
+// e = (ix - 1, iy - 1, iz - 1), q = 9 ix + 3 iy + iz; D3Q19: the same order
+// without the eight corners).  The sign pattern of every velocity is known
+// at compile time, hence so is which cells of the 4 x 3 x 3 window of each
+// face carry a weight: the window sums read LDS at immediate offsets (no
+// address arithmetic), skip the empty entries, and the weights of the stage
+// (only the non-empty entries) sit in LDS.  LDS rows are padded to 24
+// slots, which spreads the 8 x 8 cells of a wave over distinct banks.
+// ---------------------------------------------------------------------------
+struct E3 {
+    int c[3];
+};
+template <int LAT>
+__host__ __device__ constexpr E3 lat_e(int q)
+{
+    int k = 0;
+    for (int p = 0; p < 27; p++) {
+        const E3 e{{p / 9 - 1, (p / 3) % 3 - 1, p % 3 - 1}};
+        if (LAT == 19 && e.c[0] != 0 && e.c[1] != 0 && e.c[2] != 0) continue;
+        if (k == q) return e;
+        k++;
+    }
+    return E3{{0, 0, 0}};
+}
+// the lattice's weights: products of (1/6, 2/3, 1/6) per axis (D3Q27);
+// 1/3, 1/18, 1/36 for zero, one and two nonzero components (D3Q19)
+template <int LAT>
+__host__ __device__ constexpr double lat_w(int q)
+{
+    const E3 e = lat_e<LAT>(q);
+    int nz = 0;
+    double w = 1.0;
+    for (int a = 0; a < 3; a++) {
+        nz += e.c[a] != 0;
+        w *= e.c[a] != 0 ? 1.0 / 6.0 : 2.0 / 3.0;
+    }
+    if (LAT == 19) return nz == 0 ? 1.0 / 3.0 : (nz == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+    return w;
+}
+
+// window entry m of the low face along axis ax: offset oa in -2..1 along ax,
+// ob and oc in -1..1 along the other two axes (in increasing axis order)
+__host__ __device__ constexpr void win_offset(int ax, int m, int o[3])
+{
+    const int t1 = ax == 0 ? 1 : 0, t2 = ax == 2 ? 1 : 2;
+    o[0] = o[1] = o[2] = 0;
+    o[ax] = m / 9 - 2;
+    o[t1] = (m / 3) % 3 - 1;
+    o[t2] = m % 3 - 1;
+}
+// does the expansion of eq. flux_DS put a weight on window entry m?  About
+// the upwind cell U (U = -1 or 0 along ax; both when xi is parallel to the
+// face) the displacement is nonzero along ax and along every axis where xi
+// is; the expansion touches U, U +- e_a where the displacement along a is
+// nonzero, and U + e_a +- e_b where both are.
+__host__ __device__ constexpr bool in_window(const E3 e, int ax, int m)
+{
+    int o[3] = {0, 0, 0};
+    win_offset(ax, m, o);
+    bool nz[3] = {false, false, false};
+    for (int a = 0; a < 3; a++) nz[a] = a == ax || e.c[a] != 0;
+    for (int U = -1; U <= 0; U++) {
+        if ((e.c[ax] > 0 && U != -1) || (e.c[ax] < 0 && U != 0)) continue;
+        int cnt = 0;
+        bool ok = true;
+        for (int a = 0; a < 3; a++) {
+            const int p = o[a] - (a == ax ? U : 0);
+            if (p < -1 || p > 1) ok = false;
+            if (p != 0) {
+                cnt++;
+                if (!nz[a]) ok = false;
+            }
+        }
+        if (ok && cnt <= 2) return true;
+    }
+    return false;
+}
+// position of every non-empty entry in the compact weight list of a stage
+template <int LAT>
+struct WinTable {
+    short idx[3][LAT][36];
+    int total;
+};
+template <int LAT>
+__host__ __device__ constexpr WinTable<LAT> make_win()
+{
+    WinTable<LAT> w{};
+    int k = 0;
+    for (int ax = 0; ax < 3; ax++)
+        for (int q = 0; q < LAT; q++)
+            for (int m = 0; m < 36; m++) {
+                w.idx[ax][q][m] = -1;
+                if (in_window(lat_e<LAT>(q), ax, m)) w.idx[ax][q][m] = (short)k++;
+            }
+    w.total = k;
+    return w;
+}
+template <int LAT>
+inline constexpr WinTable<LAT> kWin = make_win<LAT>();
+
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    [&]<int... I>(std::integer_sequence<int, I...>) {
+        (f(std::integral_constant<int, I>{}), ...);
+    }(std::make_integer_sequence<int, N>{});
+}
+
+constexpr int LXP = 24;   // padded row of the lattice kernels' LDS tile
+constexpr int LSZ = LZ * LY * LXP;
+
+// equilibrium of lattice velocity e (storage units, as eq_store) from the
+// per-face values cu = cs u, r, dr and uu2; the products with the components
+// of e (0 or +-1) fold at compile time
+template <class T, bool DELTA, int LAT, int q>
+__device__ __forceinline__ T eq_lat(const T cu[3], T iRT, T r, T dr, T uu2)
+{
+    constexpr E3 e = lat_e<LAT>(q);
+    T eu = 0;
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+        if (e.c[d] > 0) eu += cu[d];
+        if (e.c[d] < 0) eu -= cu[d];
+    }
+    const T P = eu * iRT * ((T)1 + (T)0.5 * eu * iRT) - uu2;
+    if (DELTA) return dr + r * P;
+    return (T)lat_w<LAT>(q) * r * ((T)1 + P);
+}
+
+template <class S, bool DELTA, int LAT, int STAGE>
+__global__ void __launch_bounds__(NT) k3_stage_lat(const Args a, const S *__restrict__ Bin, const S *fh,
+                                                  const S *Ba, const S *__restrict__ G,
+                                                  const double *__restrict__ M1, S *out1, S *out2,
+                                                  double *__restrict__ Mout, const S *__restrict__ wcompact)
+{
+    using T = S;
+    constexpr int Q = LAT;
+    constexpr int NW = kWin<LAT>.total;
+    __shared__ S lds[2][LSZ];
+    __shared__ T wsh[NW];
+    const int nb8 = (a.ntiles + 7) / 8;
+    const int tile = (blockIdx.x % 8) * nb8 + blockIdx.x / 8;
+    if (tile >= a.ntiles) return;
+    const int ti = tile % a.ntx, tj = (tile / a.ntx) % a.nty, tk = tile / (a.ntx * a.nty);
+    const int t = threadIdx.x;
+    for (int k = t; k < NW; k += NT) wsh[k] = wcompact[STAGE * NW + k];
+    const int lx = t % TX, ly = (t / TX) % TY, lz = t / (TX * TY);
+    const int i = ti * TX + lx, j = tj * TY + ly, k = tk * TZ + lz;
+    const bool ok = i < a.nx && j < a.ny && k < a.nz;
+    const long long n = a.n;
+    const int ci = min(i, a.nx - 1), cj = min(j, a.ny - 1), ck = min(k, a.nz - 1);
+    const long long c = ((long long)ck * a.ny + cj) * a.nx + ci;
+
+    long long gidx[SPT];
+    int lidx[SPT];
+#pragma unroll
+    for (int r = 0; r < SPT; r++) {
+        const int s = t + r * NT;
+        gidx[r] = 0;
+        lidx[r] = 0;
+        if (s < NSLOT) {
+            const int sx = s % LX, sy = (s / LX) % LY, sz = s / (LX * LY);
+            const int gx = wrapn(ti * TX + sx - HALO, a.nx), gy = wrapn(tj * TY + sy - HALO, a.ny),
+                      gz = wrapn(tk * TZ + sz - HALO, a.nz);
+            gidx[r] = ((long long)gz * a.ny + gy) * a.nx + gx;
+            lidx[r] = (sz * LY + sy) * LXP + sx;
+        }
+    }
+    S nxt[SPT];
+    auto load = [&](int q) {
+#pragma unroll
+        for (int r = 0; r < SPT; r++)
+            if (r * NT + NT <= NSLOT || t + r * NT < NSLOT) nxt[r] = Bin[(long long)q * n + gidx[r]];
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int r = 0; r < SPT; r++)
+            if (r * NT + NT <= NSLOT || t + r * NT < NSLOT) lds[buf][lidx[r]] = nxt[r];
+    };
+
+    const double tau_c = a.tau[c];
+    const double h = a.h[STAGE];
+    T al[3][2], be[3][2];
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++) {
+#pragma unroll
+        for (int sd = 0; sd < 2; sd++) {
+            const int o = sd ? 1 : -1;
+            const int ni = ax == 0 ? wrapn(ci + o, a.nx) : ci, nj = ax == 1 ? wrapn(cj + o, a.ny) : cj,
+                      nk = ax == 2 ? wrapn(ck + o, a.nz) : ck;
+            const double tb = 0.5 * (tau_c + a.tau[((long long)nk * a.ny + nj) * a.nx + ni]);
+            al[ax][sd] = (T)(2.0 * tb / (2.0 * tb + h));
+            be[ax][sd] = (T)(h / (2.0 * tb + h));
+        }
+    }
+    // base of the cell's window: every offset below is then non-negative
+    constexpr int PITCH[3] = {1, LXP, LXP * LY};
+    constexpr int BIAS = 2 * PITCH[2] + 2 * PITCH[1] + 2 * PITCH[0];
+    const int own = ((lz + HALO) * LY + (ly + HALO)) * LXP + (lx + HALO);
+    double mf[3][2][4];
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++)
+#pragma unroll
+        for (int sd = 0; sd < 2; sd++)
+#pragma unroll
+            for (int m = 0; m < 4; m++) mf[ax][sd][m] = 0.0;
+    const double dt = a.dt;
+    const T iRT = (T)a.iRT;
+    T r1t = 0, dr1 = 0, cu1[3] = {0, 0, 0}, uu1 = 0, kw = 0;
+    if (STAGE == 1) {
+        const double r1 = M1[c], u1d[3] = {M1[n + c], M1[2 * n + c], M1[3 * n + c]};
+        r1t = (T)r1;
+        dr1 = (T)(r1 - (DELTA ? a.rho0 : 0.0));
+        for (int d = 0; d < 3; d++) cu1[d] = (T)(a.cs * u1d[d]);
+        uu1 = (T)(0.5 * (u1d[0] * u1d[0] + u1d[1] * u1d[1] + u1d[2] * u1d[2]) * a.iRT);
+        kw = (T)(6.0 * dt / (6.0 * tau_c + dt));
+    }
+    const T wl = (T)(STAGE == 0 ? dt / 3.0 : 4.0 * dt / 7.0);
+    T X[Q];
+
+    load(0);
+    store(0);
+    __syncthreads();
+    static_for<Q>([&](auto QC) {
+        constexpr int q = decltype(QC)::value;
+        if (q + 1 < Q) load(q + 1);
+        const T f = fh[(long long)q * n + c];
+        T b = 0, g = 0;
+        if (STAGE == 1) {
+            b = Ba[(long long)q * n + c];
+            g = G[(long long)q * n + c];
+        }
+        const S *B = lds[q & 1] + own - BIAS;
+        constexpr E3 e = lat_e<LAT>(q);
+        constexpr double om = DELTA ? lat_w<LAT>(q) : 1.0;
+        T acc = 0;
+        static_for<3>([&](auto AXC) {
+            constexpr int ax = decltype(AXC)::value;
+            T vlo = 0, vhi = 0;
+            static_for<36>([&](auto MC) {
+                constexpr int m = decltype(MC)::value;
+                constexpr int wi = kWin<LAT>.idx[ax][q][m];
+                if constexpr (wi >= 0) {
+                    constexpr int off = [] {
+                        int o[3] = {0, 0, 0};
+                        win_offset(ax, m, o);
+                        return o[0] * PITCH[0] + o[1] * PITCH[1] + o[2] * PITCH[2] + BIAS;
+                    }();
+                    const T wv = wsh[wi];
+                    vlo = fmat(wv, B[off], vlo);
+                    vhi = fmat(wv, B[off + PITCH[ax]], vhi);
+                }
+            });
+            const double dlo = om * (double)vlo, dhi = om * (double)vhi;
+            mf[ax][0][0] += dlo;
+            mf[ax][1][0] += dhi;
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                if (e.c[d] > 0) {
+                    mf[ax][0][d + 1] += dlo;
+                    mf[ax][1][d + 1] += dhi;
+                } else if (e.c[d] < 0) {
+                    mf[ax][0][d + 1] -= dlo;
+                    mf[ax][1][d + 1] -= dhi;
+                }
+            }
+            if constexpr (e.c[ax] != 0)
+                acc += (T)(e.c[ax] * a.cs * a.inv_d[ax]) * (al[ax][1] * vhi - al[ax][0] * vlo);
+        });
+        T own_part;
+        if (STAGE == 0) {
+            own_part = (T)1.25 * B[BIAS] - (T)0.25 * f;
+        } else {
+            const T W = -kw * (g - eq_lat<T, DELTA, LAT, q>(cu1, iRT, r1t, dr1, uu1));
+            own_part = (T)(4.0 / 7.0) * f - (T)(6.0 / 7.0) * b + (T)(9.0 / 7.0) * g + (T)0.75 * W;
+        }
+        X[q] = own_part - wl * acc;
+        // The unrolled kernel is one basic block, in which nothing ties the
+        // arithmetic to the barriers: keep this velocity's sums ahead of the
+        // barrier (else they sink past every later one and all the window
+        // values stay live until the end).
+        asm volatile("" : "+v"(X[q]));
+#pragma unroll
+        for (int ax = 0; ax < 3; ax++)
+#pragma unroll
+            for (int sd = 0; sd < 2; sd++)
+#pragma unroll
+                for (int m = 0; m < 4; m++) asm volatile("" : "+v"(mf[ax][sd][m]));
+        if (q + 1 < Q) store((q + 1) & 1);
+        __syncthreads();
+    });
+
+    // face equilibria: the beta E part of the micro-flux, along the axes where
+    // the velocity has a component
+    T fr[3][2], fdr[3][2], fcu[3][2][3], fuu[3][2];
+#pragma unroll
+    for (int ax = 0; ax < 3; ax++)
+#pragma unroll
+        for (int sd = 0; sd < 2; sd++) {
+            double rho, u[3];
+            moments_of(a, DELTA, mf[ax][sd], rho, u);
+            // the sums held the momenta over cs: u here is the velocity over cs
+            const double c2 = a.cs * a.cs;
+            fr[ax][sd] = (T)rho;
+            fdr[ax][sd] = (T)(rho - (DELTA ? a.rho0 : 0.0));
+            for (int d = 0; d < 3; d++) fcu[ax][sd][d] = (T)(c2 * u[d]);
+            fuu[ax][sd] = (T)(0.5 * c2 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * a.iRT);
+        }
+    T cid[3];
+    for (int ax = 0; ax < 3; ax++) cid[ax] = (T)(a.cs * a.inv_d[ax]);
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    static_for<Q>([&](auto QC) {
+        constexpr int q = decltype(QC)::value;
+        constexpr E3 e = lat_e<LAT>(q);
+        T lb = 0;
+#pragma unroll
+        for (int ax = 0; ax < 3; ax++) {
+            if (e.c[ax] == 0) continue;
+            const T ehi = eq_lat<T, DELTA, LAT, q>(fcu[ax][1], iRT, fr[ax][1], fdr[ax][1], fuu[ax][1]);
+            const T elo = eq_lat<T, DELTA, LAT, q>(fcu[ax][0], iRT, fr[ax][0], fdr[ax][0], fuu[ax][0]);
+            const T d = be[ax][1] * ehi - be[ax][0] * elo;
+            lb += e.c[ax] > 0 ? cid[ax] * d : -(cid[ax] * d);
+        }
+        X[q] -= wl * lb;
+        const double v = (DELTA ? lat_w<LAT>(q) : 1.0) * (double)X[q];
+        s4[0] += v;
+        for (int d = 0; d < 3; d++) {
+            if (e.c[d] > 0) s4[d + 1] += v;
+            if (e.c[d] < 0) s4[d + 1] -= v;
+        }
+    });
+    double rho, u[3];
+    moments_of(a, DELTA, s4, rho, u);
+    for (int d = 0; d < 3; d++) u[d] *= a.cs;   // s4 held the momenta over cs
+    if (!ok) return;
+    const double cc = STAGE == 0 ? (24.0 * tau_c - 5.0 * dt) / (24.0 * tau_c + 4.0 * dt)
+                                 : (12.0 * tau_c - dt) / (12.0 * tau_c + 3.0 * dt);
+    const T ct = (T)cc, cet = (T)(1.0 - cc);
+    const T rt = (T)rho, drt = (T)(rho - (DELTA ? a.rho0 : 0.0));
+    const T cuo[3] = {(T)(a.cs * u[0]), (T)(a.cs * u[1]), (T)(a.cs * u[2])};
+    const T uu = (T)(0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * a.iRT);
+    static_for<Q>([&](auto QC) {
+        constexpr int q = decltype(QC)::value;
+        out1[(long long)q * n + c] = X[q];
+        out2[(long long)q * n + c] = ct * X[q] + cet * eq_lat<T, DELTA, LAT, q>(cuo, iRT, rt, drt, uu);
+    });
+    Mout[c] = rho;
+    Mout[n + c] = u[0];
+    Mout[2 * n + c] = u[1];
+    Mout[3 * n + c] = u[2];
+}
+
+// ---------------------------------------------------------------------------
 // Per-cell kernels: state conversions and the first B_A.
 // ---------------------------------------------------------------------------
 // fhat from the physical f (FP64 [q][cell]): fhat = f - dt/4 (E - f) / tau;
@@ -474,6 +829,8 @@ struct dugks3d {
     double *xi = nullptr, *w = nullptr, *wd = nullptr;
     int *wcnt = nullptr, *woff = nullptr;
     float *wf = nullptr;
+    int lat = 0;              // 19 or 27: the velocity set is the library's lattice (k3_stage_lat)
+    void *wcomp = nullptr;    // that kernel's weights: [stage][non-empty window entries]
     std::vector<void *> allocs;
 };
 
@@ -531,6 +888,16 @@ void launch_stage(dugks3d *h, int stage)
 {
     const dim3 g((unsigned)(((h->a.ntiles + 7) / 8) * 8)), b(dk3::NT);
     S *fh = (S *)h->fh, *Ba = (S *)h->Ba, *G = (S *)h->G, *Bc = (S *)h->Bc;
+    const S *wc = (const S *)h->wcomp;
+    if (h->lat) {
+        if (stage == 0)
+            hipLaunchKernelGGL((dk3::k3_stage_lat<S, DELTA, Q, 0>), g, b, 0, h->s, h->a, Ba, fh, nullptr, nullptr,
+                               nullptr, G, Bc, h->M1, wc);
+        else
+            hipLaunchKernelGGL((dk3::k3_stage_lat<S, DELTA, Q, 1>), g, b, 0, h->s, h->a, Bc, fh, Ba, G, h->M1, fh, Ba,
+                               h->M0, wc);
+        return;
+    }
     if (stage == 0)
         hipLaunchKernelGGL((dk3::k3_stage<S, DELTA, Q, 0>), g, b, 0, h->s, h->a, Ba, fh, nullptr, nullptr, nullptr, G,
                            Bc, h->M1);
@@ -682,8 +1049,56 @@ int dugks3d_create(const dugks3d_desc *d, dugks3d_t **out)
                 }
                 wcnt[tb] = m;
             }
+    // the library's lattice order (xi = c e_q, c the largest component)?
+    {
+        double cm = 0.0;
+        for (int k = 0; k < 3 * Q; k++) cm = std::max(cm, std::fabs(d->xi[k]));
+        bool same = cm > 0;
+        for (int q = 0; q < Q && same; q++) {
+            const dk3::E3 e = Q == 27 ? dk3::lat_e<27>(q) : dk3::lat_e<19>(q);
+            const double wl = Q == 27 ? dk3::lat_w<27>(q) : dk3::lat_w<19>(q);
+            for (int ax = 0; ax < 3; ax++)
+                if (std::fabs(d->xi[ax * Q + q] - cm * e.c[ax]) > 1e-12 * cm) same = false;
+            if (std::fabs(d->w[q] - wl) > 1e-14 * wl) same = false;
+        }
+        h->lat = same ? Q : 0;
+        h->a.cs = cm;
+    }
+    std::vector<double> wcd;
+    if (h->lat) {
+        const int NW = Q == 27 ? dk3::kWin<27>.total : dk3::kWin<19>.total;
+        wcd.assign(2 * (size_t)NW, 0.0);
+        for (int st = 0; st < 2; st++)
+            for (int ax = 0; ax < 3; ax++)
+                for (int q = 0; q < Q; q++) {
+                    std::map<std::array<int, 3>, double> wm;
+                    const double x[3] = {d->xi[q], d->xi[Q + q], d->xi[2 * Q + q]};
+                    dk3::window(x, ax, hs[st], dw, kq, wm);
+                    for (int m = 0; m < 36; m++) {
+                        const int wi = Q == 27 ? dk3::kWin<27>.idx[ax][q][m] : dk3::kWin<19>.idx[ax][q][m];
+                        std::array<int, 3> o;
+                        dk3::win_offset(ax, m, o.data());
+                        auto it = wm.find(o);
+                        const double v = it == wm.end() ? 0.0 : it->second;
+                        if (wi >= 0) wcd[(size_t)st * NW + wi] = v;
+                        else if (v != 0.0) {   // a weight outside the compile-time window
+                            dugks3d_destroy(h);
+                            return err3(DUGKS_EINVAL, "interface expansion outside its window");
+                        }
+                    }
+                }
+    }
+    std::vector<float> wcf(wcd.begin(), wcd.end());
     std::vector<double> xi(d->xi, d->xi + 3 * Q), w(d->w, d->w + Q);
     int rc;
+    if (h->lat) {
+        rc = h->delta ? upload3(h, (float **)&h->wcomp, wcf.data(), wcf.size())
+                      : upload3(h, (double **)&h->wcomp, wcd.data(), wcd.size());
+        if (rc) {
+            dugks3d_destroy(h);
+            return rc;
+        }
+    }
     if ((rc = upload3(h, &h->xi, xi.data(), xi.size())) || (rc = upload3(h, &h->w, w.data(), w.size())) ||
         (rc = upload3(h, &h->tau, tau.data(), tau.size())) || (rc = upload3(h, &h->wcnt, wcnt.data(), wcnt.size())) ||
         (rc = upload3(h, &h->woff, woff.data(), woff.size())) || (rc = upload3(h, &h->wd, wd.data(), wd.size())) ||

@@ -31,8 +31,15 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _vs(lattice):
+    if lattice.endswith("_reversed"):
+        vs = getattr(C, lattice[:-9])(RT)
+        return C.VelocitySet(vs.name + "r", vs.xi[:, ::-1].copy(), vs.w[::-1].copy(), RT)
+    return getattr(C, lattice)(RT)
+
+
 def _case(shape, lattice, seed=3, tau_field=True, cfl=0.5):
-    vs = getattr(C, lattice)(RT)
+    vs = _vs(lattice)
     c = C.abc_case(0, vs, nu=0.02, ma=0.1, cfl=cfl, noise=0.3, seed=seed, shape=shape)
     tau0 = max(float(c.tau.reshape(-1)[0]), c.dt / 4.0)   # dt / tau <= 4 on coarse boxes
     # a field within +-20% (uniform), so that no cell passes the dt/tau bound
@@ -49,7 +56,9 @@ def _f0(o, case, seed):
 
 
 PARITY = [((12, 10, 7), "d3q19", 1.0), ((12, 10, 7), "d3q27", 1.0), ((9, 11, 5), "d3q19", 0.5),
-          ((8, 8, 4), "d3q27", 0.5), ((3, 4, 3), "d3q19", 1.0), ((16, 9, 9), "d3q27", 1.0)]
+          ((8, 8, 4), "d3q27", 0.5), ((3, 4, 3), "d3q19", 1.0), ((16, 9, 9), "d3q27", 1.0),
+          # the velocities in another order: the kernels with run-time window tables
+          ((12, 10, 7), "d3q19_reversed", 1.0), ((9, 11, 5), "d3q27_reversed", 0.5)]
 
 
 @pytest.mark.parametrize("shape,lattice,kq", PARITY, ids=[f"{s[0]}x{s[1]}x{s[2]}_{l}_k{k}" for s, l, k in PARITY])
