@@ -31,6 +31,8 @@ KERNEL_SOURCES = ["sweep_fast.hip", "sweep_common.h", "lattices.h", "launchers.h
                   "dugks_internal.h", "api.cpp", "../build.py"]   # (build flags shape the code too)
 # the same for the any-size kernels
 LQ_SOURCES = ["sweep_large.hip", "sweep_common.h", "ring.h", "dugks_internal.h", "api.cpp", "../build.py"]
+# the same for the three-dimensional kernels
+SOURCES_3D = ["sweep3d.hip", "dugks_internal.h", "../build.py"]
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -451,9 +453,12 @@ def run_abc3d(args):
     dom_ms = r32["stage_c_ms"] if dom == "C" else r32["stage_a_ms"]
     bytes_dom = (3 if dom == "C" else 2) * 4 * pairs
     achieved = bytes_dom / (dom_ms * 1e-3) / 1e9
+    traffic = stored_traffic(f"sweep3d_abc{args.n3}_{vs.name.lower()}_fp32delta_traffic.txt",
+                             f"stage_{dom.lower()}", SOURCES_3D)
     roofline = {"bound": "hbm", "kernel": f"stage {dom} (k3_stage_lat, STAGE={1 if dom == 'C' else 0})",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(round(traffic)),
                 "bytes_per_launch": bytes_dom, "launch_ms": round(dom_ms, 5),
                 "stage_a_ms": r32["stage_a_ms"], "stage_c_ms": r32["stage_c_ms"]}
     n = args.n3
