@@ -264,7 +264,10 @@ __global__ void __launch_bounds__(NT) k3_stage(const Args a, const S *__restrict
         } else {
             const T xq[3] = {(T)vt[q][0], (T)vt[q][1], (T)vt[q][2]};
             const T W = -kw * (g - eq_store<T, DELTA>(xq, (T)vt[q][3], iRT, r1t, dr1, u1, uu1));
-            own_part = (T)(4.0 / 7.0) * f - (T)(6.0 / 7.0) * b + (T)(9.0 / 7.0) * g + (T)0.75 * W;
+            // 4/7 f - 6/7 B_A + 9/7 G as f + 9/7 (G - f) - 6/7 (B_A - f): the
+            // rounded coefficients then act on differences only, so the
+            // constant (rho0) part of the stored deviations is kept exactly
+            own_part = f + (T)(9.0 / 7.0) * (g - f) - (T)(6.0 / 7.0) * (b - f) + (T)0.75 * W;
         }
         X[q][t] = own_part - wl * acc;
         if (q + 1 < Q) store((q + 1) & 1);
@@ -309,7 +312,8 @@ __global__ void __launch_bounds__(NT) k3_stage(const Args a, const S *__restrict
     if (!ok) return;
     const double cc = STAGE == 0 ? (24.0 * tau_c - 5.0 * dt) / (24.0 * tau_c + 4.0 * dt)
                                  : (12.0 * tau_c - dt) / (12.0 * tau_c + 3.0 * dt);
-    const T ct = (T)cc, cet = (T)(1.0 - cc);
+    // B = c X + (1 - c) E as X + (1 - c) (E - X), exact for X = E
+    const T cet = (T)(1.0 - cc);
     const T rt = (T)rho, drt = (T)(rho - (DELTA ? a.rho0 : 0.0));
     const T ut[3] = {(T)u[0], (T)u[1], (T)u[2]};
     const T uu = (T)(0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * a.iRT);
@@ -318,7 +322,7 @@ __global__ void __launch_bounds__(NT) k3_stage(const Args a, const S *__restrict
         const T o = X[q][t];
         const T xq[3] = {(T)vt[q][0], (T)vt[q][1], (T)vt[q][2]};
         out1[(long long)q * n + c] = o;
-        out2[(long long)q * n + c] = ct * o + cet * eq_store<T, DELTA>(xq, (T)vt[q][3], iRT, rt, drt, ut, uu);
+        out2[(long long)q * n + c] = o + cet * (eq_store<T, DELTA>(xq, (T)vt[q][3], iRT, rt, drt, ut, uu) - o);
     }
     Mout[c] = rho;
     Mout[n + c] = u[0];
@@ -601,7 +605,10 @@ __global__ void __launch_bounds__(NT) k3_stage_lat(const Args a, const S *__rest
             own_part = (T)1.25 * B[BIAS] - (T)0.25 * f;
         } else {
             const T W = -kw * (g - eq_lat<T, DELTA, LAT, q>(cu1, iRT, r1t, dr1, uu1));
-            own_part = (T)(4.0 / 7.0) * f - (T)(6.0 / 7.0) * b + (T)(9.0 / 7.0) * g + (T)0.75 * W;
+            // 4/7 f - 6/7 B_A + 9/7 G as f + 9/7 (G - f) - 6/7 (B_A - f): the
+            // rounded coefficients then act on differences only, so the
+            // constant (rho0) part of the stored deviations is kept exactly
+            own_part = f + (T)(9.0 / 7.0) * (g - f) - (T)(6.0 / 7.0) * (b - f) + (T)0.75 * W;
         }
         X[q] = own_part - wl * acc;
         // The unrolled kernel is one basic block, in which nothing ties the
@@ -664,14 +671,15 @@ __global__ void __launch_bounds__(NT) k3_stage_lat(const Args a, const S *__rest
     if (!ok) return;
     const double cc = STAGE == 0 ? (24.0 * tau_c - 5.0 * dt) / (24.0 * tau_c + 4.0 * dt)
                                  : (12.0 * tau_c - dt) / (12.0 * tau_c + 3.0 * dt);
-    const T ct = (T)cc, cet = (T)(1.0 - cc);
+    // B = c X + (1 - c) E as X + (1 - c) (E - X), exact for X = E
+    const T cet = (T)(1.0 - cc);
     const T rt = (T)rho, drt = (T)(rho - (DELTA ? a.rho0 : 0.0));
     const T cuo[3] = {(T)(a.cs * u[0]), (T)(a.cs * u[1]), (T)(a.cs * u[2])};
     const T uu = (T)(0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * a.iRT);
     static_for<Q>([&](auto QC) {
         constexpr int q = decltype(QC)::value;
         out1[(long long)q * n + c] = X[q];
-        out2[(long long)q * n + c] = ct * X[q] + cet * eq_lat<T, DELTA, LAT, q>(cuo, iRT, rt, drt, uu);
+        out2[(long long)q * n + c] = X[q] + cet * (eq_lat<T, DELTA, LAT, q>(cuo, iRT, rt, drt, uu) - X[q]);
     });
     Mout[c] = rho;
     Mout[n + c] = u[0];
@@ -719,7 +727,7 @@ __global__ void k3_from_f(const Args a, const double *__restrict__ f, S *__restr
     const S uu = (S)(0.5 * (uf[0] * uf[0] + uf[1] * uf[1] + uf[2] * uf[2]) * a.iRT);
     for (int q = 0; q < Q; q++) {
         fh[q * n + c] = g[q];
-        Ba[q * n + c] = (S)c1 * g[q] + (S)(1.0 - c1) * eq_tab<S, DELTA>(a, q, Q, rt, drt, ut, uu);
+        Ba[q * n + c] = g[q] + (S)(1.0 - c1) * (eq_tab<S, DELTA>(a, q, Q, rt, drt, ut, uu) - g[q]);
     }
     M0[c] = rho;
     for (int d = 0; d < 3; d++) M0[(d + 1) * n + c] = uf[d];

@@ -139,7 +139,7 @@ def test_conservation_on_a_larger_box(precision):
     s.step(50)
     r1, u1 = s.moments()
     assert np.isfinite(r1).all()
-    tol = 1e-13 if precision == dugks.FP64 else 2e-7
+    tol = 1e-13 if precision == dugks.FP64 else 1e-8
     assert abs(r1.sum() - m0) < tol * m0, (r1.sum() - m0) / m0
     assert np.abs((r1 * u1).sum(axis=(1, 2, 3)) - p0).max() < tol * m0
     s.close()
