@@ -460,8 +460,10 @@ __device__ __forceinline__ T eq_lat(const T cu[3], T iRT, T r, T dr, T uu2)
     return (T)lat_w<LAT>(q) * r * ((T)1 + P);
 }
 
+// FP64: at least two waves per SIMD (at 27 velocities stage C would take
+// 260 registers, one wave)
 template <class S, bool DELTA, int LAT, int STAGE>
-__global__ void __launch_bounds__(NT) k3_stage_lat(const Args a, const S *__restrict__ Bin, const S *fh,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DELTA ? 1 : 2, 8))) k3_stage_lat(const Args a, const S *__restrict__ Bin, const S *fh,
                                                   const S *Ba, const S *__restrict__ G,
                                                   const double *__restrict__ M1, S *out1, S *out2,
                                                   double *__restrict__ Mout, const S *__restrict__ wcompact)
