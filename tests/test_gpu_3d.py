@@ -169,3 +169,69 @@ def test_abc_flow_viscous_decay_at_32_cubed(precision):
     say(f"  rate / nu - 1 = {rate / nu - 1:.3e}")
     assert abs(rate / nu - 1.0) < 0.01
     s.close()
+
+
+def test_64_cubed_one_step_every_element_vs_oracle():
+    """A larger box (4096 tiles) in the bench's kernels: FP64 every element, FP32-delta velocity."""
+    say("3d 64^3 D3Q19 one step vs oracle")
+    case = C.abc_case(64, C.d3q19(RT), nu=0.01, ma=0.05, cfl=0.5, noise=0.3, seed=21)
+    o = Oracle3(case)
+    f0 = _f0(o, case, 47)
+    ref = o.step(o.f_to_fhat(f0))
+    s = dugks.Solver3D(case, precision=dugks.FP64)
+    s.set_state(f0)
+    s.step(1)
+    err = np.abs(s.get_fhat() - ref).max() / np.abs(ref).max()
+    say(f"  fp64 max rel {err:.3e}")
+    assert err < 1e-13, err
+    s.close()
+    s = dugks.Solver3D(case, precision=dugks.FP32_DELTA)
+    s.set_state(f0)
+    s.step(1)
+    _, u = s.moments()
+    _, u_ref = o.moments(ref)
+    du = np.abs(u - u_ref).max() / np.abs(u_ref).max()
+    say(f"  fp32-delta u max rel {du:.3e}")
+    assert du < 1e-5, du
+    s.close()
+
+
+def test_bench_configuration_128_cubed_properties():
+    """The bench's workload and launch configuration (128^3, D3Q19, FP32-delta,
+    the lattice kernels), where the oracle would take minutes per step:
+    conservation and agreement with an FP64 run from the same start; and the
+    ABC flow's viscous decay rate, measured after the initial layer of the
+    equilibrium start (t > 10 tau)."""
+    say("3d 128^3 D3Q19 bench configuration")
+    nu = 0.05
+    case = C.abc_case(128, C.d3q19(RT), nu=nu, ma=0.05, cfl=0.5)
+    tau = nu / RT
+    n1 = int(math.ceil(10 * tau / case.dt))
+    runs = {}
+    for prec, kq in ((dugks.FP32_DELTA, 1.0), (dugks.FP64, 1.0), (dugks.FP32_DELTA, 0.5)):
+        s = dugks.Solver3D(case, precision=prec, taylor_quad=kq)
+        s.init_equilibrium(case.rho, case.u)
+        r0, u0 = s.moments()
+        s.step(n1)
+        _, ua = s.moments()
+        s.step(100)
+        r1, u1 = s.moments()
+        runs[(prec, kq)] = (r0, u0, ua, r1, u1)
+        s.close()
+    r0, u0, ua, r1, u1 = runs[(dugks.FP32_DELTA, 1.0)]
+    m0 = r0.sum()
+    assert abs(r1.sum() - m0) < 1e-9 * m0
+    assert np.abs((r1 * u1).sum(axis=(1, 2, 3)) - (r0 * u0).sum(axis=(1, 2, 3))).max() < 1e-9 * m0
+    u64 = runs[(dugks.FP64, 1.0)][4]
+    gap = np.abs(u1 - u64).max() / np.abs(u64).max()
+    say(f"  fp32 vs fp64 u max rel {gap:.3e}")
+    assert gap < 1e-5
+    shape = case.u
+    amp = lambda u: float((u * shape).sum() / (shape * shape).sum())
+    rates = {}
+    for kq in (1.0, 0.5):
+        _, _, ua, _, u1 = runs[(dugks.FP32_DELTA, kq)]
+        rates[kq] = -math.log(amp(u1) / amp(ua)) / (100 * case.dt) / nu - 1.0
+        say(f"  kappa {kq}: decay rate / nu - 1 = {rates[kq]:.3e}")
+    assert abs(rates[0.5]) < 0.01   # measured -0.77%
+    assert abs(rates[1.0]) < 0.02   # measured -0.80%
