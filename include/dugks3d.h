@@ -83,7 +83,8 @@ int dugks3d_init_equilibrium(dugks3d_t *h, const double *rho, const double *u, i
  * the eight corners; the standard weights) run kernels specialised at
  * compile time; any other set of 19 or 27 velocities runs kernels that read
  * the interface-expansion windows from tables.  Both give the oracle's
- * results to rounding. */
+ * results to rounding.  There is no non-finite check (dugks_sync's flag is
+ * for the two-dimensional sweep); dugks3d_moments shows a blown-up state. */
 int dugks3d_step(dugks3d_t *h, int nsteps);
 
 /* As dugks3d_step, with HIP events around every launch; synchronises and

@@ -9,10 +9,13 @@
 //     per velocity;
 //   - every thread forms the six face values of its cell for that velocity
 //     from LDS (eqs. interfaceEvof and flux_DS: fixed window weights per
-//     axis and velocity, built on the host, read as scalars), adds them into
-//     the FP64 moments of each face, and adds the part of the micro-flux that
-//     needs no face moments, alpha fbar (eq. recover2f split into
-//     alpha fbar + beta E);
+//     axis and velocity, built on the host), adds them into the FP64 moments
+//     of each face, and adds the part of the micro-flux that needs no face
+//     moments, alpha fbar (eq. recover2f split into alpha fbar + beta E).
+//     k3_stage_lat (the library's D3Q19 / D3Q27) knows every window's shape
+//     at compile time and reads LDS at immediate offsets; k3_stage (any
+//     other order of 19 or 27 velocities) reads offsets and weights from
+//     tables;
 //   - after the last velocity the face equilibria give the beta E part, and
 //     the epilogue applies the stage's update to the thread's cell, sums the
 //     output's cell moments (FP64) and writes the next stage's transformed
@@ -24,7 +27,10 @@
 //     G = 5/4 B_A - 1/4 fhat + dt/3 L*, W = -6dt/(6 tau + dt) (G - E(G)),
 //     eq. collisionterm).
 // FP32-delta storage keeps g = f / w - rho0; the window sums and the update
-// are FP32 on g, the moments FP64.
+// are FP32 on g, the moments FP64.  The affine maps on g are written so that
+// their rounded FP32 coefficients act on differences only (X + k (E - X),
+// f + 9/7 (G - f) - 6/7 (B_A - f)): g carries rho0 implicitly, and
+// coefficients that do not sum to one in FP32 would change the mass.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
