@@ -70,7 +70,11 @@ struct Args {
     double cs;          // lattice kernels: xi = cs e_q
 };
 
-__device__ __forceinline__ int wrapn(int v, int n) { return ((v % n) + n) % n; }
+// Periodic image of v along an axis of n >= 3 cells.  Every coordinate a
+// cell inside the box reads lies in [-2, n + 1] (a halo of two), where one
+// add or subtract is exact; slots further out (past the last cell of a
+// ragged tile) only feed cells outside the box and are clamped in range.
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? min(v - n, n - 1) : v); }
 
 __device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -159,8 +163,8 @@ __global__ void __launch_bounds__(NT) k3_stage(const Args a, const S *__restrict
         gidx[r] = 0;
         if (s < NSLOT) {
             const int sx = s % LX, sy = (s / LX) % LY, sz = s / (LX * LY);
-            const int gx = wrapn(ti * TX + sx - HALO, a.nx), gy = wrapn(tj * TY + sy - HALO, a.ny),
-                      gz = wrapn(tk * TZ + sz - HALO, a.nz);
+            const int gx = wrap1(ti * TX + sx - HALO, a.nx), gy = wrap1(tj * TY + sy - HALO, a.ny),
+                      gz = wrap1(tk * TZ + sz - HALO, a.nz);
             gidx[r] = ((long long)gz * a.ny + gy) * a.nx + gx;
         }
     }
@@ -188,11 +192,12 @@ __global__ void __launch_bounds__(NT) k3_stage(const Args a, const S *__restrict
 #pragma unroll
         for (int sd = 0; sd < 2; sd++) {
             const int o = sd ? 1 : -1;
-            const int ni = ax == 0 ? wrapn(ci + o, a.nx) : ci, nj = ax == 1 ? wrapn(cj + o, a.ny) : cj,
-                      nk = ax == 2 ? wrapn(ck + o, a.nz) : ck;
+            const int ni = ax == 0 ? wrap1(ci + o, a.nx) : ci, nj = ax == 1 ? wrap1(cj + o, a.ny) : cj,
+                      nk = ax == 2 ? wrap1(ck + o, a.nz) : ck;
             const double tb = 0.5 * (tau_c + a.tau[((long long)nk * a.ny + nj) * a.nx + ni]);
-            al[ax][sd] = (T)(2.0 * tb / (2.0 * tb + h));
-            be[ax][sd] = (T)(h / (2.0 * tb + h));
+            const double rd = 1.0 / (2.0 * tb + h);
+            al[ax][sd] = (T)(2.0 * tb * rd);
+            be[ax][sd] = (T)(h * rd);
         }
     }
 
@@ -448,20 +453,27 @@ __device__ __forceinline__ void static_for(F &&f)
 constexpr int LXP = 24;   // padded row of the lattice kernels' LDS tile
 constexpr int LSZ = LZ * LY * LXP;
 
-// equilibrium of lattice velocity e (storage units, as eq_store) from the
-// per-face values cu = cs u, r, dr and uu2; the products with the components
-// of e (0 or +-1) fold at compile time
-template <class T, bool DELTA, int LAT, int q>
-__device__ __forceinline__ T eq_lat(const T cu[3], T iRT, T r, T dr, T uu2)
+// The velocity-dependent part of the equilibrium of lattice velocity e,
+// P = xi.u/RT + (xi.u)^2/(2 RT^2) - |u|^2/(2 RT), from cv = cs u / RT and
+// uu2 = |u|^2/(2 RT); the products with the components of e (0 or +-1)
+// fold at compile time
+template <class T, int LAT, int q>
+__device__ __forceinline__ T p_lat(const T cv[3], T uu2)
 {
     constexpr E3 e = lat_e<LAT>(q);
     T eu = 0;
 #pragma unroll
     for (int d = 0; d < 3; d++) {
-        if (e.c[d] > 0) eu += cu[d];
-        if (e.c[d] < 0) eu -= cu[d];
+        if (e.c[d] > 0) eu += cv[d];
+        if (e.c[d] < 0) eu -= cv[d];
     }
-    const T P = eu * iRT * ((T)1 + (T)0.5 * eu * iRT) - uu2;
+    return eu * ((T)1 + (T)0.5 * eu) - uu2;
+}
+// equilibrium of lattice velocity e in storage units (as eq_store)
+template <class T, bool DELTA, int LAT, int q>
+__device__ __forceinline__ T eq_lat(const T cv[3], T r, T dr, T uu2)
+{
+    const T P = p_lat<T, LAT, q>(cv, uu2);
     if (DELTA) return dr + r * P;
     return (T)lat_w<LAT>(q) * r * ((T)1 + P);
 }
@@ -501,8 +513,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DELTA ?
         lidx[r] = 0;
         if (s < NSLOT) {
             const int sx = s % LX, sy = (s / LX) % LY, sz = s / (LX * LY);
-            const int gx = wrapn(ti * TX + sx - HALO, a.nx), gy = wrapn(tj * TY + sy - HALO, a.ny),
-                      gz = wrapn(tk * TZ + sz - HALO, a.nz);
+            const int gx = wrap1(ti * TX + sx - HALO, a.nx), gy = wrap1(tj * TY + sy - HALO, a.ny),
+                      gz = wrap1(tk * TZ + sz - HALO, a.nz);
             gidx[r] = ((long long)gz * a.ny + gy) * a.nx + gx;
             lidx[r] = (sz * LY + sy) * LXP + sx;
         }
@@ -521,17 +533,18 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DELTA ?
 
     const double tau_c = a.tau[c];
     const double h = a.h[STAGE];
-    T al[3][2], be[3][2];
+    // alpha of each face; beta = 1 - alpha is formed after the loop (fewer
+    // registers held through it)
+    T al[3][2];
 #pragma unroll
     for (int ax = 0; ax < 3; ax++) {
 #pragma unroll
         for (int sd = 0; sd < 2; sd++) {
             const int o = sd ? 1 : -1;
-            const int ni = ax == 0 ? wrapn(ci + o, a.nx) : ci, nj = ax == 1 ? wrapn(cj + o, a.ny) : cj,
-                      nk = ax == 2 ? wrapn(ck + o, a.nz) : ck;
+            const int ni = ax == 0 ? wrap1(ci + o, a.nx) : ci, nj = ax == 1 ? wrap1(cj + o, a.ny) : cj,
+                      nk = ax == 2 ? wrap1(ck + o, a.nz) : ck;
             const double tb = 0.5 * (tau_c + a.tau[((long long)nk * a.ny + nj) * a.nx + ni]);
             al[ax][sd] = (T)(2.0 * tb / (2.0 * tb + h));
-            be[ax][sd] = (T)(h / (2.0 * tb + h));
         }
     }
     // base of the cell's window: every offset below is then non-negative
@@ -546,13 +559,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DELTA ?
 #pragma unroll
             for (int m = 0; m < 4; m++) mf[ax][sd][m] = 0.0;
     const double dt = a.dt;
-    const T iRT = (T)a.iRT;
-    T r1t = 0, dr1 = 0, cu1[3] = {0, 0, 0}, uu1 = 0, kw = 0;
+    T r1t = 0, dr1 = 0, cv1[3] = {0, 0, 0}, uu1 = 0, kw = 0;
     if (STAGE == 1) {
         const double r1 = M1[c], u1d[3] = {M1[n + c], M1[2 * n + c], M1[3 * n + c]};
         r1t = (T)r1;
         dr1 = (T)(r1 - (DELTA ? a.rho0 : 0.0));
-        for (int d = 0; d < 3; d++) cu1[d] = (T)(a.cs * u1d[d]);
+        for (int d = 0; d < 3; d++) cv1[d] = (T)(a.cs * u1d[d] * a.iRT);
         uu1 = (T)(0.5 * (u1d[0] * u1d[0] + u1d[1] * u1d[1] + u1d[2] * u1d[2]) * a.iRT);
         kw = (T)(6.0 * dt / (6.0 * tau_c + dt));
     }
@@ -612,7 +624,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DELTA ?
         if (STAGE == 0) {
             own_part = (T)1.25 * B[BIAS] - (T)0.25 * f;
         } else {
-            const T W = -kw * (g - eq_lat<T, DELTA, LAT, q>(cu1, iRT, r1t, dr1, uu1));
+            const T W = -kw * (g - eq_lat<T, DELTA, LAT, q>(cv1, r1t, dr1, uu1));
             // 4/7 f - 6/7 B_A + 9/7 G as f + 9/7 (G - f) - 6/7 (B_A - f): the
             // rounded coefficients then act on differences only, so the
             // constant (rho0) part of the stored deviations is kept exactly
@@ -635,23 +647,28 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DELTA ?
     });
 
     // face equilibria: the beta E part of the micro-flux, along the axes where
-    // the velocity has a component
-    T fr[3][2], fdr[3][2], fcu[3][2][3], fuu[3][2];
+    // the velocity has a component.  Each face's weight in the output,
+    // K = wl (cs / width) beta, is folded into its density terms: the face
+    // adds K (D + R P) with D = rho - rho0 (DELTA) or rho, R = rho, and P as
+    // in p_lat (times w for the f-form)
+    T fcv[3][2][3], fuu[3][2], fkr[3][2], fkd[3];
 #pragma unroll
-    for (int ax = 0; ax < 3; ax++)
+    for (int ax = 0; ax < 3; ax++) {
+        double kd[2];
 #pragma unroll
         for (int sd = 0; sd < 2; sd++) {
             double rho, u[3];
             moments_of(a, DELTA, mf[ax][sd], rho, u);
             // the sums held the momenta over cs: u here is the velocity over cs
             const double c2 = a.cs * a.cs;
-            fr[ax][sd] = (T)rho;
-            fdr[ax][sd] = (T)(rho - (DELTA ? a.rho0 : 0.0));
-            for (int d = 0; d < 3; d++) fcu[ax][sd][d] = (T)(c2 * u[d]);
+            const double K = (double)wl * a.cs * a.inv_d[ax] * (1.0 - (double)al[ax][sd]);
+            fkr[ax][sd] = (T)(K * rho);
+            kd[sd] = K * (rho - (DELTA ? a.rho0 : 0.0));
+            for (int d = 0; d < 3; d++) fcv[ax][sd][d] = (T)(c2 * u[d] * a.iRT);
             fuu[ax][sd] = (T)(0.5 * c2 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * a.iRT);
         }
-    T cid[3];
-    for (int ax = 0; ax < 3; ax++) cid[ax] = (T)(a.cs * a.inv_d[ax]);
+        fkd[ax] = (T)(kd[1] - kd[0]);
+    }
     double s4[4] = {0.0, 0.0, 0.0, 0.0};
     static_for<Q>([&](auto QC) {
         constexpr int q = decltype(QC)::value;
@@ -660,12 +677,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DELTA ?
 #pragma unroll
         for (int ax = 0; ax < 3; ax++) {
             if (e.c[ax] == 0) continue;
-            const T ehi = eq_lat<T, DELTA, LAT, q>(fcu[ax][1], iRT, fr[ax][1], fdr[ax][1], fuu[ax][1]);
-            const T elo = eq_lat<T, DELTA, LAT, q>(fcu[ax][0], iRT, fr[ax][0], fdr[ax][0], fuu[ax][0]);
-            const T d = be[ax][1] * ehi - be[ax][0] * elo;
-            lb += e.c[ax] > 0 ? cid[ax] * d : -(cid[ax] * d);
+            const T phi = p_lat<T, LAT, q>(fcv[ax][1], fuu[ax][1]);
+            const T plo = p_lat<T, LAT, q>(fcv[ax][0], fuu[ax][0]);
+            T d = fkd[ax] + fkr[ax][1] * phi - fkr[ax][0] * plo;
+            if (!DELTA) d *= (T)lat_w<LAT>(q);
+            lb += e.c[ax] > 0 ? d : -d;
         }
-        X[q] -= wl * lb;
+        X[q] -= lb;
         const double v = (DELTA ? lat_w<LAT>(q) : 1.0) * (double)X[q];
         s4[0] += v;
         for (int d = 0; d < 3; d++) {
@@ -682,12 +700,12 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DELTA ?
     // B = c X + (1 - c) E as X + (1 - c) (E - X), exact for X = E
     const T cet = (T)(1.0 - cc);
     const T rt = (T)rho, drt = (T)(rho - (DELTA ? a.rho0 : 0.0));
-    const T cuo[3] = {(T)(a.cs * u[0]), (T)(a.cs * u[1]), (T)(a.cs * u[2])};
+    const T cvo[3] = {(T)(a.cs * u[0] * a.iRT), (T)(a.cs * u[1] * a.iRT), (T)(a.cs * u[2] * a.iRT)};
     const T uu = (T)(0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * a.iRT);
     static_for<Q>([&](auto QC) {
         constexpr int q = decltype(QC)::value;
         out1[(long long)q * n + c] = X[q];
-        out2[(long long)q * n + c] = X[q] + cet * (eq_lat<T, DELTA, LAT, q>(cuo, iRT, rt, drt, uu) - X[q]);
+        out2[(long long)q * n + c] = X[q] + cet * (eq_lat<T, DELTA, LAT, q>(cvo, rt, drt, uu) - X[q]);
     });
     Mout[c] = rho;
     Mout[n + c] = u[0];
