@@ -490,13 +490,17 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DELTA ?
     constexpr int Q = LAT;
     constexpr int NW = kWin<LAT>.total;
     __shared__ S lds[2][LSZ];
-    __shared__ T wsh[NW];
+    // the weights in 16-byte chunks: a wave reads four (FP64: two) uniform
+    // weights per LDS instruction, at immediate offsets from one base
+    constexpr int VW = 16 / (int)sizeof(T);
+    using V = T __attribute__((ext_vector_type(VW)));
+    __shared__ V wsh[(NW + VW - 1) / VW];
     const int nb8 = (a.ntiles + 7) / 8;
     const int tile = (blockIdx.x % 8) * nb8 + blockIdx.x / 8;
     if (tile >= a.ntiles) return;
     const int ti = tile % a.ntx, tj = (tile / a.ntx) % a.nty, tk = tile / (a.ntx * a.nty);
     const int t = threadIdx.x;
-    for (int k = t; k < NW; k += NT) wsh[k] = wcompact[STAGE * NW + k];
+    for (int k = t; k < NW; k += NT) wsh[k / VW][k % VW] = wcompact[STAGE * NW + k];
     const int lx = t % TX, ly = (t / TX) % TY, lz = t / (TX * TY);
     const int i = ti * TX + lx, j = tj * TY + ly, k = tk * TZ + lz;
     const bool ok = i < a.nx && j < a.ny && k < a.nz;
@@ -599,7 +603,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DELTA ?
                         win_offset(ax, m, o);
                         return o[0] * PITCH[0] + o[1] * PITCH[1] + o[2] * PITCH[2] + BIAS;
                     }();
-                    const T wv = wsh[wi];
+                    const T wv = wsh[wi / VW][wi % VW];
                     vlo = fmat(wv, B[off], vlo);
                     vhi = fmat(wv, B[off + PITCH[ax]], vhi);
                 }
