@@ -77,7 +77,7 @@ int dugks3d_set_state(dugks3d_t *h, const double *f, int mem);
 int dugks3d_init_equilibrium(dugks3d_t *h, const double *rho, const double *u, int mem);
 
 /* Advance nsteps T3S3 steps (asynchronous on the stream): two kernels per
- * step, one per stage, each over tiles of 8 x 8 x 4 cells.  Velocity sets
+ * step, one per stage, each over tiles of 16 x 8 x 2 cells.  Velocity sets
  * equal to the library's D3Q19 or D3Q27 (xi = c e_q with e_q in the order of
  * cases.d3q27: q = 9 (ex+1) + 3 (ey+1) + (ez+1), D3Q19 the same order without
  * the eight corners; the standard weights) run kernels specialised at

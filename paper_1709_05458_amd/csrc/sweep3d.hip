@@ -2,7 +2,9 @@
 // box of uniform cells, for gfx950.
 //
 // One step is two kernels, one per stage; each runs a block of 256 threads
-// (four waves) over a tile of 8 x 8 x 4 cells, one cell per thread:
+// (four waves) over a tile of 16 x 8 x 2 cells, one cell per thread (rows
+// of 16 cells: a wave's own-cell loads and stores cover whole 64-byte
+// segments):
 //   - the loop over velocities is outermost: the stage's transformed state
 //     B_q (fbar^{+,h} of eqs. f_bar_1_6 / fbp_5_12, kept in HBM) of the tile
 //     and a halo of two cells is staged in LDS, double-buffered, one barrier
@@ -46,7 +48,7 @@
 
 namespace dk3 {
 
-constexpr int TX = 8, TY = 8, TZ = 4, HALO = 2;
+constexpr int TX = 16, TY = 8, TZ = 2, HALO = 2;
 constexpr int LX = TX + 2 * HALO, LY = TY + 2 * HALO, LZ = TZ + 2 * HALO;
 constexpr int NSLOT = LX * LY * LZ;           // 1152 LDS slots per velocity
 constexpr int NT = TX * TY * TZ;              // 256 threads
@@ -348,8 +350,8 @@ __global__ void __launch_bounds__(NT) k3_stage(const Args a, const S *__restrict
 // at compile time, hence so is which cells of the 4 x 3 x 3 window of each
 // face carry a weight: the window sums read LDS at immediate offsets (no
 // address arithmetic), skip the empty entries, and the weights of the stage
-// (only the non-empty entries) sit in LDS.  LDS rows are padded to 24
-// slots, which spreads the 8 x 8 cells of a wave over distinct banks.
+// (only the non-empty entries) sit in LDS.  LDS rows are padded to 48
+// slots, which puts the two 16-cell rows of each half-wave on distinct banks.
 // ---------------------------------------------------------------------------
 struct E3 {
     int c[3];
@@ -450,7 +452,7 @@ __device__ __forceinline__ void static_for(F &&f)
     }(std::make_integer_sequence<int, N>{});
 }
 
-constexpr int LXP = 24;   // padded row of the lattice kernels' LDS tile
+constexpr int LXP = 48;   // padded row of the lattice kernels' LDS tile
 constexpr int LSZ = LZ * LY * LXP;
 
 // The velocity-dependent part of the equilibrium of lattice velocity e,

@@ -2,7 +2,7 @@
 ABI) against the three-dimensional oracle, on the same seeded inputs.
 
 FP64: every (q, cell) of fhat after one and after three steps within 1e-13 of
-its scale, on boxes with ragged tiles (the kernels tile 8 x 8 x 4 cells), a
+its scale, on boxes with ragged tiles (the kernels tile 16 x 8 x 2 cells), a
 varying relaxation field, both velocity sets and both coefficients of the
 quadratic term.  FP32-delta storage: velocity within 1e-5 of its scale.
 Larger boxes, where the oracle would be slow: conservation, and the ABC
@@ -172,7 +172,7 @@ def test_abc_flow_viscous_decay_at_32_cubed(precision):
 
 
 def test_64_cubed_one_step_every_element_vs_oracle():
-    """A larger box (4096 tiles) in the bench's kernels: FP64 every element, FP32-delta velocity."""
+    """A larger box (1024 tiles) in the bench's kernels: FP64 every element, FP32-delta velocity."""
     say("3d 64^3 D3Q19 one step vs oracle")
     case = C.abc_case(64, C.d3q19(RT), nu=0.01, ma=0.05, cfl=0.5, noise=0.3, seed=21)
     o = Oracle3(case)
