@@ -78,6 +78,24 @@ struct Args {
 // ragged tile) only feed cells outside the box and are clamped in range.
 __device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? min(v - n, n - 1) : v); }
 
+// Tile coordinates of a tile's place in the launch order: x fastest, then y
+// within a band of up to YB tile rows, then z, then the bands.  Tiles that
+// share a halo along y or z then run close together in time (and on one
+// XCD), so the shared planes are still in its L2.
+constexpr int YB = 2;
+__device__ __forceinline__ void tile_coords(const Args &a, int tile, int &ti, int &tj, int &tk)
+{
+    const int ntz = a.ntiles / (a.ntx * a.nty);
+    const int per_band = a.ntx * ntz * YB;   // tiles of a full band
+    const int b = tile / per_band;
+    const int r = tile - b * per_band;
+    const int hb = min(YB, a.nty - b * YB);   // rows of this band
+    ti = r % a.ntx;
+    const int s = r / a.ntx;
+    tj = b * YB + s % hb;
+    tk = s / hb;
+}
+
 __device__ __forceinline__ float fmat(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmat(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -141,7 +159,8 @@ __global__ void __launch_bounds__(NT) k3_stage(const Args a, const S *__restrict
     const int nb8 = (a.ntiles + 7) / 8;
     const int tile = (blockIdx.x % 8) * nb8 + blockIdx.x / 8;
     if (tile >= a.ntiles) return;
-    const int ti = tile % a.ntx, tj = (tile / a.ntx) % a.nty, tk = tile / (a.ntx * a.nty);
+    int ti, tj, tk;
+    tile_coords(a, tile, ti, tj, tk);
     const int t = threadIdx.x;
     if (t < Q) {
         for (int d = 0; d < 3; d++) {
@@ -500,7 +519,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DELTA ?
     const int nb8 = (a.ntiles + 7) / 8;
     const int tile = (blockIdx.x % 8) * nb8 + blockIdx.x / 8;
     if (tile >= a.ntiles) return;
-    const int ti = tile % a.ntx, tj = (tile / a.ntx) % a.nty, tk = tile / (a.ntx * a.nty);
+    int ti, tj, tk;
+    tile_coords(a, tile, ti, tj, tk);
     const int t = threadIdx.x;
     for (int k = t; k < NW; k += NT) wsh[k / VW][k % VW] = wcompact[STAGE * NW + k];
     const int lx = t % TX, ly = (t / TX) % TY, lz = t / (TX * TY);
