@@ -235,3 +235,51 @@ def test_bench_configuration_128_cubed_properties():
         say(f"  kappa {kq}: decay rate / nu - 1 = {rates[kq]:.3e}")
     assert abs(rates[0.5]) < 0.01   # measured -0.77%
     assert abs(rates[1.0]) < 0.02   # measured -0.80%
+
+
+def test_box_beyond_2_31_elements_matches_a_thin_box():
+    """Maximum-size case: 256 x 256 x 1800 cells, D3Q19 FP32-delta, so that
+    velocity x cell offsets pass 2^31 (2.24e9 per array).  Every cell's
+    arithmetic depends only on its neighbourhood and the run's constants, so
+    a state uniform along z evolves, bit for bit, as the same state on a box
+    of 4 cells along z: the moments of every z plane of the large box must
+    equal those of the thin box exactly."""
+    props = torch.cuda.get_device_properties(0)
+    if props.total_memory < 96 * 2 ** 30:   # pragma: no cover
+        pytest.skip("needs about 70 GB of device memory")
+    vs = C.d3q19(RT)
+    nx = ny = 256
+    h = 2.0 * math.pi / nx
+    x = (np.arange(nx) + 0.5) * h
+    X, Y = np.meshgrid(x, x)   # (ny, nx)
+    ux = 0.05 * np.sin(X) * np.cos(Y) + 0.005 * C.normal(61, nx * ny).reshape(ny, nx)
+    uy = -0.05 * np.cos(X) * np.sin(Y) + 0.005 * C.normal(62, nx * ny).reshape(ny, nx)
+    uz = 0.02 * np.sin(X + Y)
+    rho = 1.0 + 0.01 * C.normal(63, nx * ny).reshape(ny, nx)
+    dt = 0.5 * h / vs.cmax
+    tau0 = 0.02
+
+    def run(nz):
+        shape = (nz, ny, nx)
+        r = np.ascontiguousarray(np.broadcast_to(rho, shape))
+        u = np.ascontiguousarray(np.broadcast_to(np.stack([ux, uy, uz])[:, None], (3,) + shape))
+        case = C.Case3(f"z-uniform {nz}", (nx, ny, nz), (2 * math.pi, 2 * math.pi, nz * h), vs, dt,
+                       np.array(tau0), r, u)
+        say(f"3d z-uniform box {nx}x{ny}x{nz} D3Q19 fp32-delta, {vs.nq * nx * ny * nz} elements per array")
+        s = dugks.Solver3D(case, precision=dugks.FP32_DELTA)
+        s.init_equilibrium(r, u)
+        del r, u
+        s.step(3)
+        out = s.moments()
+        s.close()
+        return out
+
+    rs, us = run(4)
+    assert np.ptp(rs, axis=0).max() == 0.0 and np.ptp(us, axis=1).max() == 0.0
+    assert np.abs(us[0, 0] - ux).max() > 1e-6   # three steps changed the state
+    rb, ub = run(1800)
+    assert vs.nq * rb.size > 2 ** 31
+    assert np.array_equal(rb, np.broadcast_to(rs[:1], rb.shape))
+    del rb
+    for d in range(3):
+        assert np.array_equal(ub[d], np.broadcast_to(us[d, :1], ub[d].shape)), d
