@@ -249,9 +249,10 @@ def test_box_beyond_2_31_elements_matches_a_thin_box():
         pytest.skip("needs about 70 GB of device memory")
     vs = C.d3q19(RT)
     nx = ny = 256
-    h = 2.0 * math.pi / nx
-    x = (np.arange(nx) + 0.5) * h
-    X, Y = np.meshgrid(x, x)   # (ny, nx)
+    # a power-of-two cell width: L / n is exactly h on every axis of both boxes
+    h = 1.0 / 32
+    x = (np.arange(nx) + 0.5) * h * (2.0 * math.pi / (nx * h))
+    X, Y = np.meshgrid(x, x)   # (ny, nx), phases over one period
     ux = 0.05 * np.sin(X) * np.cos(Y) + 0.005 * C.normal(61, nx * ny).reshape(ny, nx)
     uy = -0.05 * np.cos(X) * np.sin(Y) + 0.005 * C.normal(62, nx * ny).reshape(ny, nx)
     uz = 0.02 * np.sin(X + Y)
@@ -263,7 +264,7 @@ def test_box_beyond_2_31_elements_matches_a_thin_box():
         shape = (nz, ny, nx)
         r = np.ascontiguousarray(np.broadcast_to(rho, shape))
         u = np.ascontiguousarray(np.broadcast_to(np.stack([ux, uy, uz])[:, None], (3,) + shape))
-        case = C.Case3(f"z-uniform {nz}", (nx, ny, nz), (2 * math.pi, 2 * math.pi, nz * h), vs, dt,
+        case = C.Case3(f"z-uniform {nz}", (nx, ny, nz), (nx * h, ny * h, nz * h), vs, dt,
                        np.array(tau0), r, u)
         say(f"3d z-uniform box {nx}x{ny}x{nz} D3Q19 fp32-delta, {vs.nq * nx * ny * nz} elements per array")
         s = dugks.Solver3D(case, precision=dugks.FP32_DELTA)

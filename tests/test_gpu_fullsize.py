@@ -87,3 +87,51 @@ def test_fullsize_sampled_cells_against_oracle(precision):
     else:
         # K FP32 steps: a few float roundings of O(1) deviation variables each
         assert worst_g < 4e-6 and worst_u < 2e-6 * u0
+
+
+def test_grid_beyond_2_31_elements_matches_a_thin_grid():
+    """Maximum-size case of the benchmark's kernels: 2048 x 28672 cells of
+    D2Q37 in FP32-delta storage, so that velocity x cell offsets pass 2^31
+    (2.17e9 per array).  Every cell's arithmetic depends only on its
+    neighbourhood and the run's constants, so a state uniform along y evolves,
+    bit for bit, as the same state on a grid 64 cells tall: every row of the
+    large grid's moments must equal those of the thin grid exactly."""
+    props = torch.cuda.get_device_properties(0)
+    if props.total_memory < 96 * 2 ** 30:   # pragma: no cover
+        pytest.skip("needs about 40 GB of device memory")
+    vs = C.d2q37(1.0 / 3.0)
+    nx = 2048
+    # a power-of-two cell width: the face coordinates of both grids are exact,
+    # so both are uniform to the last bit (a rounded spacing would make the
+    # library treat the tall grid as non-uniform and use other kernels)
+    h = 1.0 / 256
+    x = (np.arange(nx) + 0.5) * h
+    k = 2.0 * np.pi / (nx * h)
+    ux = 0.05 * np.sin(k * x) + 0.005 * C.normal(71, nx)
+    uy = 0.03 * np.cos(2 * k * x) + 0.005 * C.normal(72, nx)
+    rho = 1.0 + 0.01 * C.normal(73, nx)
+    dt = 0.5 * h / vs.cmax
+    tau0 = 0.02
+
+    def run(ny):
+        rows = lambda a: np.ascontiguousarray(np.broadcast_to(a, (ny, nx)))
+        case = C.Case(f"y-uniform {ny}", C.uniform_grid(nx, ny, nx * h, ny * h), vs, dt, np.array(tau0),
+                      (C.BC_PERIODIC,) * 4, np.zeros((4, 2)), rows(rho), rows(ux), rows(uy), 1.0, 3, {})
+        say(f"y-uniform grid {nx}x{ny} D2Q37 fp32-delta, {vs.nq * nx * ny} elements per array")
+        s = dugks.Solver(case, dugks.FP32_DELTA)
+        s.init_equilibrium(case.rho, case.ux, case.uy)
+        s.step(3)
+        out = s.moments()
+        desc = s.describe()
+        say(desc)
+        assert "non-uniform" not in desc
+        s.close()
+        return out
+
+    thin = run(64)
+    assert all(np.ptp(a, axis=0).max() == 0.0 for a in thin)
+    assert np.abs(thin[1][0] - ux).max() > 1e-6   # three steps changed the state
+    big = run(28672)
+    assert vs.nq * big[0].size > 2 ** 31
+    for a, b in zip(big, thin):
+        assert np.array_equal(a, np.broadcast_to(b[:1], a.shape))
