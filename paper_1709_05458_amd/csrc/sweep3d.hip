@@ -500,9 +500,11 @@ __device__ __forceinline__ T eq_lat(const T cv[3], T r, T dr, T uu2)
 }
 
 // FP64: at least two waves per SIMD (at 27 velocities stage C would take
-// 260 registers, one wave)
+// 260 registers, one wave).  FP32 D3Q27 stage C: three (174 registers would
+// give two; at 168 a few values spill, and the stage runs 9% faster)
 template <class S, bool DELTA, int LAT, int STAGE>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DELTA ? 1 : 2, 8))) k3_stage_lat(const Args a, const S *__restrict__ Bin, const S *fh,
+__global__ void __launch_bounds__(NT)
+    __attribute__((amdgpu_waves_per_eu(DELTA ? (LAT == 27 && STAGE == 1 ? 3 : 1) : 2, 8))) k3_stage_lat(const Args a, const S *__restrict__ Bin, const S *fh,
                                                   const S *Ba, const S *__restrict__ G,
                                                   const double *__restrict__ M1, S *out1, S *out2,
                                                   double *__restrict__ Mout, const S *__restrict__ wcompact)
